@@ -1,0 +1,256 @@
+"""Python front end of the CPU FP64 oracle (test infrastructure only).
+
+Thin ctypes wrappers around ``liboracle.so`` (built from ``rlb_oracle.cpp`` by
+``oracle/build.py``) returning numpy arrays.  Only the test suite, the smoke
+check and the CPU-baseline leg of the benchmark import this module; the GPU
+product path never does.
+
+Arrays of the distribution use the layout ``F[s, x]`` with ``s = i*q_xi + j``
+(radial node ``i`` outer, polar node ``j`` inner) and hold the weight-free
+values ``F = 2*pi*exp(p)*f`` at the nodes.
+"""
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+class _Tube(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("z_min", ctypes.c_double), ("z_max", ctypes.c_double),
+                ("q_xi", ctypes.c_int32), ("q_p", ctypes.c_int32),
+                ("n_v", ctypes.c_int32), ("n_p", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("dt", ctypes.c_double), ("T0", ctypes.c_double),
+                ("weno_eps", ctypes.c_double)]
+
+
+class _State(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_double), ("n", ctypes.c_double), ("u", ctypes.c_double)]
+
+
+@dataclass
+class Tube:
+    """One shock tube, in the paper's problem-statement terms.
+
+    ``dt`` defaults to ``min(cfl*dz, dt_tau_max*tau)``: the CFL condition with
+    the speed of light as the largest speed, capped by the relaxation time.
+    """
+    nx: int = 800
+    q_xi: int = 8
+    q_p: int = 3
+    n_v: int = 5
+    n_p: int = 2
+    tau: float = 1e-2
+    z_min: float = -0.5
+    z_max: float = 0.5
+    cfl: float = 0.5
+    dt_tau_max: float = 0.5
+    dt: float = 0.0
+    T0: float = 1.0
+    weno_eps: float = 1e-6
+
+    @property
+    def dz(self) -> float:
+        return (self.z_max - self.z_min) / self.nx
+
+    @property
+    def step_dt(self) -> float:
+        if self.dt > 0:
+            return self.dt
+        return min(self.cfl * self.dz, self.dt_tau_max * self.tau)
+
+    @property
+    def Q(self) -> int:
+        return self.q_xi * self.q_p
+
+    def z(self) -> np.ndarray:
+        return self.z_min + (np.arange(self.nx) + 0.5) * self.dz
+
+    def _c(self) -> _Tube:
+        return _Tube(self.nx, self.z_min, self.z_max, self.q_xi, self.q_p, self.n_v, self.n_p,
+                     self.tau, self.step_dt, self.T0, self.weno_eps)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from .build import build as _build
+            _build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        tp = ctypes.POINTER(_Tube)
+        lib.oracle_gauss_legendre.argtypes = [ctypes.c_int, dp, dp]
+        lib.oracle_gauss_laguerre1.argtypes = [ctypes.c_int, dp, dp]
+        lib.oracle_legendre.argtypes = [ctypes.c_int, ctypes.c_double]
+        lib.oracle_legendre.restype = ctypes.c_double
+        lib.oracle_laguerre1.argtypes = [ctypes.c_int, ctypes.c_double]
+        lib.oracle_laguerre1.restype = ctypes.c_double
+        lib.oracle_weno5.argtypes = [ctypes.c_double] * 6
+        lib.oracle_weno5.restype = ctypes.c_double
+        lib.oracle_landau.argtypes = [dp, dp]
+        lib.oracle_feq_coefficients.argtypes = [tp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        lib.oracle_feq_nodes.argtypes = [tp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
+        lib.oracle_tables.argtypes = [tp, dp, dp, dp, dp]
+        lib.oracle_init.argtypes = [tp, _State, _State, dp]
+        lib.oracle_step.argtypes = [tp, dp, ctypes.c_int64]
+        lib.oracle_rhs.argtypes = [tp, dp, dp]
+        lib.oracle_fields.argtypes = [tp, dp, dp]
+        lib.oracle_step_tangent.argtypes = [tp, dp, dp, ctypes.c_double, ctypes.c_int64]
+        lib.oracle_init_tangent.argtypes = [tp, _State, _State, _State, _State, dp, dp]
+        lib.oracle_fields_tangent.argtypes = [tp, dp, dp, dp, dp]
+        lib.oracle_num_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _check(rc):
+    if rc != 0:
+        raise ValueError("oracle call rejected its arguments")
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
+
+
+def gauss_legendre(q: int):
+    x = np.zeros(q); w = np.zeros(q)
+    _check(_load().oracle_gauss_legendre(q, _ptr(x), _ptr(w)))
+    return x, w
+
+
+def gauss_laguerre1(q: int):
+    x = np.zeros(q); w = np.zeros(q)
+    _check(_load().oracle_gauss_laguerre1(q, _ptr(x), _ptr(w)))
+    return x, w
+
+
+def legendre(n: int, x: float) -> float:
+    return _load().oracle_legendre(n, x)
+
+
+def laguerre1(n: int, x: float) -> float:
+    return _load().oracle_laguerre1(n, x)
+
+
+def weno5(v, eps=1e-6) -> float:
+    return _load().oracle_weno5(*[float(a) for a in v], float(eps))
+
+
+def landau(m):
+    """(N0, Nz, T00, T0z, Tzz) -> dict(e, v, gamma, u, n, T)."""
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    out = np.zeros(6)
+    _load().oracle_landau(_ptr(m), _ptr(out))
+    return dict(zip(("e", "v", "gamma", "u", "n", "T"), out))
+
+
+def feq_coefficients(tube: Tube, n: float, T: float, u: float) -> np.ndarray:
+    """Projection coefficients C[k, l] (k <= n_v, l <= n_p)."""
+    C = np.zeros((tube.n_v + 1) * (tube.n_p + 1))
+    _check(_load().oracle_feq_coefficients(ctypes.byref(tube._c()), n, T, u, _ptr(C)))
+    return C.reshape(tube.n_v + 1, tube.n_p + 1)
+
+
+def feq_nodes(tube: Tube, n: float, T: float, u: float) -> np.ndarray:
+    """Weight-free truncated equilibrium at the Q nodes, shape [Q]."""
+    F = np.zeros(tube.Q)
+    _check(_load().oracle_feq_nodes(ctypes.byref(tube._c()), n, T, u, _ptr(F)))
+    return F
+
+
+def tables(tube: Tube):
+    """(xi, w_xi, p, w_p) quadrature tables of the tube."""
+    xi = np.zeros(tube.q_xi); wxi = np.zeros(tube.q_xi)
+    p = np.zeros(tube.q_p); wp = np.zeros(tube.q_p)
+    _check(_load().oracle_tables(ctypes.byref(tube._c()), _ptr(xi), _ptr(wxi), _ptr(p), _ptr(wp)))
+    return xi, wxi, p, wp
+
+
+def init(tube: Tube, left, right) -> np.ndarray:
+    """Initial distribution F[Q, nx] for left/right states (P, n, u)."""
+    F = np.zeros((tube.Q, tube.nx))
+    _check(_load().oracle_init(ctypes.byref(tube._c()), _State(*left), _State(*right), _ptr(F)))
+    return F
+
+
+def step(tube: Tube, F: np.ndarray, nsteps: int) -> np.ndarray:
+    """Returns F advanced by ``nsteps`` SSP-RK3 steps (input untouched)."""
+    G = np.array(F, dtype=np.float64, order="C", copy=True)
+    _check(_load().oracle_step(ctypes.byref(tube._c()), _ptr(G), int(nsteps)))
+    return G
+
+
+def rhs(tube: Tube, F: np.ndarray) -> np.ndarray:
+    G = np.ascontiguousarray(F, dtype=np.float64)
+    out = np.zeros_like(G)
+    _check(_load().oracle_rhs(ctypes.byref(tube._c()), _ptr(G), _ptr(out)))
+    return out
+
+
+FIELD_NAMES = ("N0", "Nz", "T00", "T0z", "Tzz", "e", "n", "v", "T", "Nabs")
+
+
+def fields(tube: Tube, F: np.ndarray) -> np.ndarray:
+    """Per-cell fields [10, nx]: N0, Nz, T00, T0z, Tzz, e, n, v, T, |N|."""
+    G = np.ascontiguousarray(F, dtype=np.float64)
+    out = np.zeros((10, tube.nx))
+    _check(_load().oracle_fields(ctypes.byref(tube._c()), _ptr(G), _ptr(out)))
+    return out
+
+
+def step_tangent(tube: Tube, F: np.ndarray, dF: np.ndarray, dtau: float, nsteps: int):
+    """Tangent-linear model: (F, dF) advanced by ``nsteps`` with tau moving by dtau."""
+    G = np.array(F, dtype=np.float64, order="C", copy=True)
+    dG = np.array(dF, dtype=np.float64, order="C", copy=True)
+    _check(_load().oracle_step_tangent(ctypes.byref(tube._c()), _ptr(G), _ptr(dG), float(dtau), int(nsteps)))
+    return G, dG
+
+
+def init_tangent(tube: Tube, left, right, dleft, dright):
+    F = np.zeros((tube.Q, tube.nx)); dF = np.zeros((tube.Q, tube.nx))
+    _check(_load().oracle_init_tangent(ctypes.byref(tube._c()), _State(*left), _State(*right),
+                                       _State(*dleft), _State(*dright), _ptr(F), _ptr(dF)))
+    return F, dF
+
+
+def fields_tangent(tube: Tube, F: np.ndarray, dF: np.ndarray):
+    G = np.ascontiguousarray(F, dtype=np.float64)
+    dG = np.ascontiguousarray(dF, dtype=np.float64)
+    out = np.zeros((10, tube.nx)); dout = np.zeros((10, tube.nx))
+    _check(_load().oracle_fields_tangent(ctypes.byref(tube._c()), _ptr(G), _ptr(dG), _ptr(out), _ptr(dout)))
+    return out, dout
+
+
+def run(tube: Tube, left, right, nsteps: int) -> np.ndarray:
+    """Initial state then ``nsteps`` steps; returns F[Q, nx]."""
+    return step(tube, init(tube, left, right), nsteps)
+
+
+def moments_weights(tube: Tube) -> np.ndarray:
+    """Moment basis B[5, Q]: N0..Tzz = B @ F[:, x]."""
+    xi, wxi, p, wp = tables(tube)
+    B = np.zeros((5, tube.Q))
+    t3, t4 = tube.T0 ** 3, tube.T0 ** 4
+    for i in range(tube.q_p):
+        for j in range(tube.q_xi):
+            w = wp[i] * wxi[j]
+            s = i * tube.q_xi + j
+            B[:, s] = w * np.array([t3 * p[i], t3 * p[i] * xi[j], t4 * p[i] ** 2,
+                                    t4 * p[i] ** 2 * xi[j], t4 * p[i] ** 2 * xi[j] ** 2])
+    return B
+
+
+SOD_LEFT = (1.0, 1.0, 0.0)
+SOD_RIGHT = (0.1, 0.125, 0.0)
+PI = math.pi
