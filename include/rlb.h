@@ -1,0 +1,188 @@
+/*
+ * rlb.h -- C interface of the MI355X (gfx950) implementation of the
+ * quadrature-based finite-difference relativistic lattice Boltzmann model for
+ * massless particles of Blaga & Ambrus, "Quadrature-based Lattice Boltzmann
+ * Model for Relativistic Flows" (arXiv:1608.03004).
+ *
+ * One time step advances, for every cell and every point of the momentum
+ * quadrature, the 1D Boltzmann equation with the Anderson-Witting collision
+ * term (section "Relativistic lattice Boltzmann equation", eq. Boltz):
+ *   moments N^mu, T^{mu nu} -> Landau frame (e, u^mu, n, T) -> truncated
+ *   Maxwell-Juettner equilibrium (eq. feqtrunc) -> WENO5 upwind advection and
+ *   relaxation -> third-order SSP Runge-Kutta (section "Numerical results").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All functions return an rlb_status; 0 is success, negative is an error.
+ *   Argument errors are detected synchronously on the host before any device
+ *   work is queued; the lattice is then unchanged.  rlb_last_error() gives a
+ *   human-readable reason for the last failure on a lattice.
+ * - Device pointers are plain HIP device addresses.  The caller owns the
+ *   workspace (rlb_bind) and every state/adjoint buffer it passes in; the
+ *   library owns only the opaque handle and its host-side tables.  The library
+ *   never allocates device memory.
+ * - Work is queued asynchronously on the HIP stream given to rlb_bind (NULL
+ *   means the legacy default stream).  Calls documented as "synchronizes" wait
+ *   for that stream.  A lattice must not be used from two threads at once.
+ * - A non-physical cell state met on the device (e <= 0, n <= 0, |v| >= 1 or
+ *   NaN in the Landau matching) sets a sticky flag; the next synchronizing call
+ *   (rlb_moments, rlb_totals, rlb_check) returns RLB_ERR_NONPHYSICAL.
+ *
+ * Layouts
+ * -------
+ * Quadrature point s = i*q_xi + j, with i the Gauss-Laguerre (|p|) node and j
+ * the Gauss-Legendre (xi = cos theta) node, both in ascending order.  The
+ * azimuthal angle drops out of the 1D problem exactly and is not stored.
+ * A state buffer holds, for every tube, the weight-free distribution values
+ *   F_s(x) = 2*pi * exp(p_i) * f(p_i, xi_j; z_x)      (p in units of T0)
+ * in rows of ld_x >= nx elements: element (s, x) of tube t is at
+ *   state + off[t] + s*ld[t] + x, in FP64 or FP32 as chosen at creation.
+ * rlb_state_layout() returns off[t] and ld[t] (in elements).  The quadrature-
+ * weighted distribution of the paper is f_s = w^p_i w^xi_j F_s.
+ */
+#ifndef RLB_H
+#define RLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RLB_OK = 0,
+  RLB_ERR_INVALID_ARG = -1, /* an argument is out of range; nothing was done  */
+  RLB_ERR_NONPHYSICAL = -2, /* the sticky device flag is set (see above)       */
+  RLB_ERR_HIP = -3,         /* a HIP runtime call failed                        */
+  RLB_ERR_STATE = -4,       /* call out of order (e.g. step before bind/init)   */
+  RLB_ERR_UNSTABLE_DT = -5  /* dt*|rate| outside the explicit RK3 stability box */
+} rlb_status;
+
+typedef enum { RLB_FP64 = 0, RLB_FP32 = 1 } rlb_precision;
+
+/* Creation flags. */
+#define RLB_WITH_ADJOINT 1u /* reserve workspace for rlb_adjoint_step */
+
+/*
+ * One shock tube, following the problem statement of the paper:
+ *   grid      -- "spatial domain set to unity", 1 x 1 x L_z nodes (section
+ *                Numerical results): cell-centred cells on [z_min, z_max],
+ *                dz = (z_max - z_min)/nx;
+ *   q_xi, q_p -- quadrature orders (section "Discretization of the momentum
+ *                space"; Q_p = 3 suffices for N^mu and T^{mu nu}, section
+ *                Riemann problem); q_p <= 8;
+ *   n_v, n_p  -- truncation orders of eq. feqtrunc (the paper uses 5 and 2);
+ *                n_v <= 7 and n_p < q_p;  N^mu and T^{mu nu} of the
+ *                equilibrium are exact when n_p + 2 <= 2 q_p - 1 and
+ *                n_v + 2 <= 2 q_xi - 1, both required;
+ *   tau       -- constant relaxation time (section Relativistic LB equation);
+ *                +INFINITY gives the collisionless (ballistic) limit;
+ *   dt        -- > 0: explicit time step; 0: min(cfl*dz, dt_tau_max*tau)
+ *                (CFL with the speed of light, section Numerical results);
+ *   T0        -- reference temperature of eq. feq (results do not depend on
+ *                it in exact arithmetic);
+ *   weno_eps  -- WENO5 epsilon applied to the weight-free F.
+ * rlb_tube_defaults() fills the paper's values (nx 800, q_xi 8, q_p 3,
+ * n_v 5, n_p 2, tau 1e-2, z in [-0.5, 0.5], cfl 0.5, dt_tau_max 0.5, T0 1,
+ * weno_eps 1e-6).
+ */
+typedef struct {
+  int32_t nx;
+  int32_t q_xi, q_p;
+  int32_t n_v, n_p;
+  int32_t reserved0;
+  double z_min, z_max;
+  double tau;
+  double cfl;
+  double dt_tau_max;
+  double dt;
+  double T0;
+  double weno_eps;
+} rlb_tube_desc;
+
+/* Macroscopic state (pressure P, density n, velocity u^z) of one side of the
+ * Riemann problem (section Riemann problem, eq. condinit). */
+typedef struct {
+  double P, n, u;
+} rlb_state;
+
+/* Launch schedule of the stage kernels (chosen by the autotuner). */
+typedef struct {
+  int32_t tile;        /* cells per workgroup: 128 or 256                       */
+  int32_t persistent;  /* 1: grid sized to the device, blocks loop over tiles   */
+  int32_t blocks_per_cu; /* persistent grid = blocks_per_cu * CU count           */
+  int32_t graph_steps; /* >0: replay time steps from a captured hipGraph of this many steps */
+} rlb_schedule;
+
+typedef struct rlb_lattice rlb_lattice;
+
+rlb_status rlb_tube_defaults(rlb_tube_desc* desc);
+
+/* Validates the tubes and builds the host tables; no device work.
+ * tubes: ntubes >= 1 descriptors (copied).  prec: arithmetic of the
+ * distribution (the Landau matching and the moment records are always FP64).
+ * flags: RLB_WITH_ADJOINT or 0.  *out receives the handle. */
+rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision prec, uint32_t flags,
+                      rlb_lattice** out);
+rlb_status rlb_destroy(rlb_lattice* lat);
+
+/* Bytes of device workspace the lattice needs (256-byte aligned base). */
+rlb_status rlb_workspace_size(const rlb_lattice* lat, size_t* bytes);
+/* Attaches caller-owned device memory and the stream; uploads the tables
+ * (queued on the stream).  May be called again to move the lattice. */
+rlb_status rlb_bind(rlb_lattice* lat, void* workspace, size_t bytes, void* hip_stream);
+rlb_status rlb_set_stream(rlb_lattice* lat, void* hip_stream);
+rlb_status rlb_set_schedule(rlb_lattice* lat, const rlb_schedule* sched);
+rlb_status rlb_get_schedule(const rlb_lattice* lat, rlb_schedule* sched);
+
+/* Initial condition of eq. condinit: the truncated equilibrium of `left` for
+ * cell centres z < 0 and of `right` otherwise.  tube = -1 sets every tube.
+ * Resets the tube's time to 0.  Requires P > 0, n > 0. */
+rlb_status rlb_set_initial_state(rlb_lattice* lat, int32_t tube, rlb_state left, rlb_state right);
+
+/* Per-tube initial states in one call: left[t], right[t] for t < ntubes
+ * (ntubes must equal the lattice's tube count). */
+rlb_status rlb_set_initial_states(rlb_lattice* lat, int32_t ntubes, const rlb_state* left, const rlb_state* right);
+
+/* Advances every tube by nsteps full SSP-RK3 steps (3 stage launches each).
+ * Asynchronous. */
+rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps);
+
+/* Per-cell fields of one tube, FP64, 10 rows of ld >= nx:
+ * N0, Nz, T00, T0z, Tzz, e, n, v, T, |N| = sqrt(N0^2 - Nz^2).
+ * rlb_fields writes a device buffer asynchronously; rlb_moments writes a host
+ * buffer, synchronizes, and reports the sticky flag. */
+rlb_status rlb_fields(rlb_lattice* lat, int32_t tube, double* dev_out, int64_t ld);
+rlb_status rlb_moments(rlb_lattice* lat, int32_t tube, double* host_out, int64_t ld);
+/* FP64 totals dz*sum(N0), dz*sum(T00), dz*sum(T0z); synchronizes. */
+rlb_status rlb_totals(rlb_lattice* lat, int32_t tube, double out[3]);
+/* Synchronizes and reports the sticky flag; RLB_OK if clear. */
+rlb_status rlb_check(rlb_lattice* lat);
+
+/* State buffers: element count of a full state and each tube's placement. */
+rlb_status rlb_state_elems(const rlb_lattice* lat, int64_t* elems);
+rlb_status rlb_state_layout(const rlb_lattice* lat, int32_t tube, int64_t* off, int64_t* ld);
+/* Copies the current state to / from a caller device buffer (asynchronous).
+ * rlb_set_state also recomputes the moment records. */
+rlb_status rlb_get_state(rlb_lattice* lat, void* dst_device);
+rlb_status rlb_set_state(rlb_lattice* lat, const void* src_device);
+
+/* Per-tube parameters and time. */
+rlb_status rlb_set_tau(rlb_lattice* lat, int32_t tube, double tau);
+rlb_status rlb_tube_info(const rlb_lattice* lat, int32_t tube, double* dt, double* time, int32_t* Q);
+
+/* Quadrature tables of a tube as used on the device (host copies):
+ * xi[q_xi], w_xi[q_xi], p[q_p], w_p[q_p]. */
+rlb_status rlb_tables(const rlb_lattice* lat, int32_t tube, double* xi, double* w_xi, double* p, double* w_p);
+
+/* Plain device copy kernel (bandwidth calibration); asynchronous. */
+rlb_status rlb_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+
+const char* rlb_status_string(rlb_status st);
+const char* rlb_last_error(const rlb_lattice* lat);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RLB_H */

@@ -1,0 +1,782 @@
+// Host side of the C interface declared in include/rlb.h: validation, the
+// momentum-quadrature tables, the device workspace layout, work lists and
+// launch schedules, and the hipGraph replay of time steps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/rlb.h"
+#include "quadrature.h"
+#include "rlb_internal.h"
+
+using namespace rlb;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+struct Group {
+  int qpt, nvt;
+  int item_begin, item_end;  // range in the item list
+};
+
+}  // namespace
+
+struct rlb_lattice {
+  std::vector<rlb_tube_desc> desc;
+  int ntubes = 0;
+  rlb_precision prec = RLB_FP64;
+  uint32_t flags = 0;
+  size_t rsize = 8;
+
+  // host tables
+  std::vector<TubeDev> tubes;
+  std::vector<double> jtab_d, itab, aux_d;
+  std::vector<float> jtab_f, aux_f;
+  int aux_pairs = 0;
+  std::vector<std::vector<double>> xi, wxi, p, wp;  // per tube (host copies)
+
+  // layout
+  int64_t state_elems = 0, rec_elems = 0;
+  int max_items = 0, max_ldx = 0;
+  size_t off_F[3] = {0, 0, 0}, off_rec[3] = {0, 0, 0};
+  size_t off_tubes = 0, off_jtab = 0, off_itab = 0, off_aux = 0, off_items = 0, off_sides = 0, off_mask = 0,
+         off_flag = 0, off_fields = 0, off_totals = 0, total = 0;
+
+  // binding
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;
+  bool initialised = false;
+
+  // schedule and work lists
+  rlb_schedule sched = {256, 0, 4, 0};
+  std::vector<WorkItem> items;
+  std::vector<Group> groups;
+  int cu_count = 0;
+
+  // graph replay
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_steps = 0;
+
+  std::vector<double> time;
+  std::vector<double> sides_h;
+  std::vector<int32_t> mask_h;
+  std::string err;
+
+  template <typename T>
+  T* dev(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+};
+
+namespace {
+
+rlb_status fail(rlb_lattice* L, rlb_status st, const std::string& msg) {
+  if (L) L->err = msg; else g_create_error = msg;
+  return st;
+}
+
+rlb_status hip_fail(rlb_lattice* L, hipError_t e, const char* where) {
+  return fail(L, RLB_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(L, expr)                                     \
+  do {                                                       \
+    hipError_t _e = (expr);                                  \
+    if (_e != hipSuccess) return hip_fail((L), _e, #expr);   \
+  } while (0)
+
+void kernel_group(int qp, int nv, int* qpt, int* nvt) {
+  if (nv <= 5 && qp <= 3) { *qpt = 3; *nvt = 5; }
+  else if (nv <= 5 && qp == 4) { *qpt = 4; *nvt = 5; }
+  else { *qpt = 8; *nvt = 7; }
+}
+
+double tube_dt(const rlb_tube_desc& d) {
+  const double dz = (d.z_max - d.z_min) / d.nx;
+  if (d.dt > 0) return d.dt;
+  return std::min(d.cfl * dz, d.dt_tau_max * d.tau);
+}
+
+rlb_status validate(const rlb_tube_desc& d, int k, std::string& msg) {
+  char buf[256];
+  auto bad = [&](const char* what) {
+    std::snprintf(buf, sizeof buf, "tube %d: %s", k, what);
+    msg = buf;
+    return RLB_ERR_INVALID_ARG;
+  };
+  if (d.nx < 8 || d.nx > (1 << 28)) return bad("nx must be in [8, 2^28]");
+  if (d.q_xi < 1 || d.q_xi > 4096) return bad("q_xi must be in [1, 4096]");
+  if (d.q_p < 1 || d.q_p > kMaxQp) return bad("q_p must be in [1, 8]");
+  if (d.n_v < 0 || d.n_v > kMaxNv) return bad("n_v must be in [0, 7]");
+  if (d.n_p < 0 || d.n_p >= d.q_p) return bad("n_p must satisfy 0 <= n_p < q_p");
+  if (d.n_p + 2 > 2 * d.q_p - 1) return bad("q_p too small to integrate T^{mu nu} of the equilibrium exactly");
+  if (d.n_v + 2 > 2 * d.q_xi - 1) return bad("q_xi too small to integrate T^{mu nu} of the equilibrium exactly");
+  if (!(d.z_max > d.z_min) || !std::isfinite(d.z_min) || !std::isfinite(d.z_max)) return bad("need z_min < z_max");
+  if (!(d.tau > 0)) return bad("tau must be > 0 (+inf allowed)");
+  if (!(d.T0 > 0) || !std::isfinite(d.T0)) return bad("T0 must be > 0");
+  if (!(d.weno_eps > 0)) return bad("weno_eps must be > 0");
+  if (d.dt < 0 || !std::isfinite(d.dt)) return bad("dt must be >= 0");
+  if (d.dt == 0 && !(d.cfl > 0 && std::isfinite(d.cfl))) return bad("cfl must be > 0");
+  if (d.dt == 0 && !(d.dt_tau_max > 0)) return bad("dt_tau_max must be > 0");
+  const double dt = tube_dt(d), dz = (d.z_max - d.z_min) / d.nx;
+  if (!(dt > 0) || !std::isfinite(dt)) return bad("time step is not a positive number");
+  if (dt > 1.5 * dz) {
+    std::snprintf(buf, sizeof buf, "tube %d: dt/dz = %g exceeds the WENO5/RK3 stability limit 1.5", k, dt / dz);
+    msg = buf;
+    return RLB_ERR_UNSTABLE_DT;
+  }
+  if (dt > 2.5 * d.tau) {
+    std::snprintf(buf, sizeof buf, "tube %d: dt/tau = %g exceeds the RK3 stability limit 2.5", k, dt / d.tau);
+    msg = buf;
+    return RLB_ERR_UNSTABLE_DT;
+  }
+  return RLB_OK;
+}
+
+void build_items(rlb_lattice* L) {
+  const int tile = L->sched.tile;
+  std::map<std::pair<int, int>, std::vector<int>> by_group;
+  for (int t = 0; t < L->ntubes; ++t) {
+    int qpt, nvt;
+    kernel_group(L->desc[t].q_p, L->desc[t].n_v, &qpt, &nvt);
+    by_group[{qpt, nvt}].push_back(t);
+  }
+  L->items.clear();
+  L->groups.clear();
+  for (auto& kv : by_group) {
+    Group g;
+    g.qpt = kv.first.first;
+    g.nvt = kv.first.second;
+    g.item_begin = static_cast<int>(L->items.size());
+    std::vector<std::pair<int64_t, WorkItem>> tmp;
+    for (int t : kv.second) {
+      const int64_t cost = int64_t(L->desc[t].q_xi) * L->desc[t].q_p;
+      for (int x0 = 0; x0 < L->desc[t].nx; x0 += tile) tmp.push_back({cost, WorkItem{t, x0}});
+    }
+    // most expensive tiles first (balances persistent grids); stable within a tube
+    std::stable_sort(tmp.begin(), tmp.end(), [](const auto& a, const auto& b) { return a.first > b.first; });
+    for (auto& e : tmp) L->items.push_back(e.second);
+    g.item_end = static_cast<int>(L->items.size());
+    L->groups.push_back(g);
+  }
+}
+
+void drop_graph(rlb_lattice* L) {
+  if (L->graph_exec) (void)hipGraphExecDestroy(L->graph_exec);
+  if (L->graph) (void)hipGraphDestroy(L->graph);
+  L->graph_exec = nullptr;
+  L->graph = nullptr;
+  L->graph_steps = 0;
+}
+
+rlb_status upload(rlb_lattice* L, size_t off, const void* src, size_t bytes) {
+  if (!bytes) return RLB_OK;
+  HIP_TRY(L, hipMemcpyAsync(L->ws + off, src, bytes, hipMemcpyHostToDevice, L->stream));
+  HIP_TRY(L, hipStreamSynchronize(L->stream));
+  return RLB_OK;
+}
+
+LaunchShape shape(const rlb_lattice* L, const Group& g) {
+  LaunchShape ls;
+  ls.tile = L->sched.tile;
+  const int n = g.item_end - g.item_begin;
+  ls.grid = n;
+  if (L->sched.persistent) ls.grid = std::max(1, std::min(n, L->sched.blocks_per_cu * std::max(1, L->cu_count)));
+  return ls;
+}
+
+rlb_status enqueue_steps(rlb_lattice* L, hipStream_t s, int64_t nsteps) {
+  const bool fp32 = L->prec == RLB_FP32;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    for (int stage = 1; stage <= 3; ++stage) {
+      for (const Group& g : L->groups) {
+        const LaunchShape ls = shape(L, g);
+        const int fin = stage == 1 ? 0 : (stage == 2 ? 1 : 2);
+        const int fout = stage == 1 ? 1 : (stage == 2 ? 2 : 0);
+        const int rin = fin, rout = fout;
+        hipError_t e;
+        if (fp32) {
+          StageArgs<float> a;
+          a.tubes = L->dev<TubeDev>(L->off_tubes);
+          a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
+          a.nitems = g.item_end - g.item_begin;
+          a.stage = stage;
+          a.aux_pairs = L->aux_pairs;
+          a.jtab = L->dev<float>(L->off_jtab);
+          a.itab = L->dev<double>(L->off_itab);
+          a.aux = L->dev<float>(L->off_aux);
+          a.fin = L->dev<float>(L->off_F[fin]);
+          a.fn = L->dev<float>(L->off_F[0]);
+          a.fout = L->dev<float>(L->off_F[fout]);
+          a.rec_in = L->dev<double>(L->off_rec[rin]);
+          a.rec_out = L->dev<double>(L->off_rec[rout]);
+          a.flag = L->dev<unsigned>(L->off_flag);
+          e = launch_stage(1, g.qpt, g.nvt, ls, &a, s);
+        } else {
+          StageArgs<double> a;
+          a.tubes = L->dev<TubeDev>(L->off_tubes);
+          a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
+          a.nitems = g.item_end - g.item_begin;
+          a.stage = stage;
+          a.aux_pairs = L->aux_pairs;
+          a.jtab = L->dev<double>(L->off_jtab);
+          a.itab = L->dev<double>(L->off_itab);
+          a.aux = L->dev<double>(L->off_aux);
+          a.fin = L->dev<double>(L->off_F[fin]);
+          a.fn = L->dev<double>(L->off_F[0]);
+          a.fout = L->dev<double>(L->off_F[fout]);
+          a.rec_in = L->dev<double>(L->off_rec[rin]);
+          a.rec_out = L->dev<double>(L->off_rec[rout]);
+          a.flag = L->dev<unsigned>(L->off_flag);
+          e = launch_stage(0, g.qpt, g.nvt, ls, &a, s);
+        }
+        if (e != hipSuccess) return hip_fail(L, e, "stage kernel launch");
+      }
+    }
+  }
+  return RLB_OK;
+}
+
+rlb_status ensure_graph(rlb_lattice* L) {
+  const int G = L->sched.graph_steps;
+  if (L->graph_exec && L->graph_steps == G) return RLB_OK;
+  drop_graph(L);
+  hipStream_t cap;
+  HIP_TRY(L, hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(cap);
+    return hip_fail(L, e, "hipStreamBeginCapture");
+  }
+  rlb_status st = enqueue_steps(L, cap, G);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(cap, &graph);
+  (void)hipStreamDestroy(cap);
+  if (st != RLB_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(L, e, "hipStreamEndCapture");
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return hip_fail(L, e, "hipGraphInstantiate");
+  }
+  L->graph = graph;
+  L->graph_exec = exec;
+  L->graph_steps = G;
+  return RLB_OK;
+}
+
+bool check_tube(const rlb_lattice* L, int32_t tube) { return tube >= 0 && tube < L->ntubes; }
+
+rlb_status need_ready(rlb_lattice* L, bool need_init) {
+  if (!L) return RLB_ERR_INVALID_ARG;
+  if (!L->ws) return fail(L, RLB_ERR_STATE, "no workspace bound (call rlb_bind)");
+  if (need_init && !L->initialised) return fail(L, RLB_ERR_STATE, "no state (call rlb_set_initial_state or rlb_set_state)");
+  return RLB_OK;
+}
+
+rlb_status read_flag(rlb_lattice* L) {
+  unsigned flag = 0;
+  HIP_TRY(L, hipMemcpyAsync(&flag, L->ws + L->off_flag, sizeof flag, hipMemcpyDeviceToHost, L->stream));
+  HIP_TRY(L, hipStreamSynchronize(L->stream));
+  if (flag & kFlagNonphysical)
+    return fail(L, RLB_ERR_NONPHYSICAL, "a cell reached a non-physical state (e <= 0, n <= 0, |v| >= 1 or NaN)");
+  return RLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rlb_status rlb_tube_defaults(rlb_tube_desc* d) {
+  if (!d) return RLB_ERR_INVALID_ARG;
+  std::memset(d, 0, sizeof *d);
+  d->nx = 800;
+  d->q_xi = 8;
+  d->q_p = 3;
+  d->n_v = 5;
+  d->n_p = 2;
+  d->z_min = -0.5;
+  d->z_max = 0.5;
+  d->tau = 1e-2;
+  d->cfl = 0.5;
+  d->dt_tau_max = 0.5;
+  d->dt = 0.0;
+  d->T0 = 1.0;
+  d->weno_eps = 1e-6;
+  return RLB_OK;
+}
+
+rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision prec, uint32_t flags,
+                      rlb_lattice** out) {
+  if (!out) return fail(nullptr, RLB_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!tubes || ntubes < 1) return fail(nullptr, RLB_ERR_INVALID_ARG, "need ntubes >= 1 descriptors");
+  if (prec != RLB_FP64 && prec != RLB_FP32) return fail(nullptr, RLB_ERR_INVALID_ARG, "unknown precision");
+  if (flags & ~RLB_WITH_ADJOINT) return fail(nullptr, RLB_ERR_INVALID_ARG, "unknown flags");
+  for (int k = 0; k < ntubes; ++k) {
+    std::string msg;
+    rlb_status st = validate(tubes[k], k, msg);
+    if (st != RLB_OK) return fail(nullptr, st, msg);
+  }
+  rlb_lattice* L = new rlb_lattice();
+  L->desc.assign(tubes, tubes + ntubes);
+  L->ntubes = ntubes;
+  L->prec = prec;
+  L->flags = flags;
+  L->rsize = prec == RLB_FP32 ? 4 : 8;
+  L->time.assign(ntubes, 0.0);
+  L->sides_h.assign(6 * size_t(ntubes), 0.0);
+  L->mask_h.assign(ntubes, 0);
+
+  // quadrature tables, shared between tubes with equal orders
+  std::map<int, int> jrow_of;                          // q_xi -> first row
+  std::map<std::tuple<int, double>, int> irow_of;      // (q_p, T0) -> first row
+  L->xi.resize(ntubes); L->wxi.resize(ntubes); L->p.resize(ntubes); L->wp.resize(ntubes);
+  int64_t f_off = 0, rec_off = 0;
+  for (int t = 0; t < ntubes; ++t) {
+    const rlb_tube_desc& d = tubes[t];
+    std::vector<double> x, w, px, pw;
+    if (!gauss_legendre_rule(d.q_xi, x, w) || !gauss_laguerre1_rule(d.q_p, px, pw)) {
+      delete L;
+      return fail(nullptr, RLB_ERR_INVALID_ARG, "quadrature construction failed");
+    }
+    L->xi[t] = x; L->wxi[t] = w; L->p[t] = px; L->wp[t] = pw;
+    int jrow, irow;
+    auto jt = jrow_of.find(d.q_xi);
+    if (jt == jrow_of.end()) {
+      jrow = static_cast<int>(L->jtab_d.size() / kJStride);
+      for (int j = 0; j < d.q_xi; ++j) {
+        double row[kJStride];
+        row[0] = x[j];
+        row[1] = w[j];
+        row[2] = w[j] * x[j];
+        row[3] = w[j] * x[j] * x[j];
+        for (int k = 0; k <= kMaxNv; ++k) row[4 + k] = legendre_value(k, x[j]);
+        L->jtab_d.insert(L->jtab_d.end(), row, row + kJStride);
+      }
+      jrow_of[d.q_xi] = jrow;
+    } else {
+      jrow = jt->second;
+    }
+    auto key = std::make_tuple(d.q_p, d.T0);
+    auto it = irow_of.find(key);
+    if (it == irow_of.end()) {
+      irow = static_cast<int>(L->itab.size() / kIStride);
+      const double t3 = d.T0 * d.T0 * d.T0, t4 = t3 * d.T0;
+      for (int i = 0; i < d.q_p; ++i) {
+        double row[kIStride];
+        row[0] = px[i];
+        row[1] = pw[i];
+        row[2] = t3 * pw[i] * px[i];
+        row[3] = t4 * pw[i] * px[i] * px[i];
+        for (int l = 0; l <= kMaxNp; ++l) row[4 + l] = laguerre1_value(l, px[i]);
+        L->itab.insert(L->itab.end(), row, row + kIStride);
+      }
+      irow_of[key] = irow;
+    } else {
+      irow = it->second;
+    }
+    TubeDev td;
+    std::memset(&td, 0, sizeof td);
+    td.nx = d.nx;
+    td.ldx = (d.nx + 63) / 64 * 64;
+    td.qx = d.q_xi;
+    td.qp = d.q_p;
+    td.nv = d.n_v;
+    td.np = d.n_p;
+    td.jrow = jrow;
+    td.irow = irow;
+    td.z_min = d.z_min;
+    td.dz = (d.z_max - d.z_min) / d.nx;
+    td.dz_inv = 1.0 / td.dz;
+    td.dt = tube_dt(d);
+    td.tau_inv = 1.0 / d.tau;
+    td.T0 = d.T0;
+    td.weno_eps = d.weno_eps;
+    int qpt, nvt;
+    kernel_group(d.q_p, d.n_v, &qpt, &nvt);
+    td.group = qpt * 16 + nvt;
+    td.f_off = f_off;
+    td.rec_off = rec_off;
+    f_off += int64_t(d.q_xi) * d.q_p * td.ldx;
+    rec_off += 5 * int64_t(td.ldx);
+    L->max_ldx = std::max(L->max_ldx, td.ldx);
+    L->tubes.push_back(td);
+  }
+  L->state_elems = f_off;
+  L->rec_elems = rec_off;
+  L->jtab_f.assign(L->jtab_d.begin(), L->jtab_d.end());
+
+  // auxiliary projection rule: symmetric pairs of a Gauss-Legendre rule
+  const int M = prec == RLB_FP32 ? 2 * kAuxPairsFP32 : 2 * kAuxPairsFP64;
+  std::vector<double> ax, aw;
+  gauss_legendre_rule(M, ax, aw);
+  L->aux_pairs = M / 2;
+  for (int a = 0; a < M / 2; ++a) {
+    const int j = M / 2 + a;  // positive nodes
+    double row[kAuxStride];
+    row[0] = ax[j];
+    for (int k = 0; k <= kMaxNv; ++k) row[1 + k] = aw[j] * (2 * k + 1) / 2.0 * legendre_value(k, ax[j]);
+    for (int k = kMaxNv + 2; k < kAuxStride; ++k) row[k] = 0.0;
+    L->aux_d.insert(L->aux_d.end(), row, row + kAuxStride);
+  }
+  L->aux_f.assign(L->aux_d.begin(), L->aux_d.end());
+
+  // work-list bound: smallest tile
+  int64_t max_items = 0;
+  for (auto& d : L->desc) max_items += (d.nx + 127) / 128;
+  L->max_items = static_cast<int>(max_items);
+
+  // workspace layout
+  size_t o = 0;
+  for (int k = 0; k < 3; ++k) { L->off_F[k] = o; o = align256(o + L->state_elems * L->rsize); }
+  for (int k = 0; k < 3; ++k) { L->off_rec[k] = o; o = align256(o + L->rec_elems * 8); }
+  L->off_tubes = o; o = align256(o + L->tubes.size() * sizeof(TubeDev));
+  L->off_jtab = o; o = align256(o + L->jtab_d.size() * L->rsize);
+  L->off_itab = o; o = align256(o + L->itab.size() * 8);
+  L->off_aux = o; o = align256(o + L->aux_d.size() * L->rsize);
+  L->off_items = o; o = align256(o + size_t(L->max_items) * sizeof(WorkItem));
+  L->off_sides = o; o = align256(o + L->sides_h.size() * 8);
+  L->off_mask = o; o = align256(o + L->mask_h.size() * 4);
+  L->off_flag = o; o = align256(o + 16);
+  L->off_fields = o; o = align256(o + 10 * size_t(L->max_ldx) * 8);
+  L->off_totals = o; o = align256(o + 4 * 8);
+  L->total = o;
+
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) L->cu_count = prop.multiProcessorCount;
+  }
+  build_items(L);
+  *out = L;
+  return RLB_OK;
+}
+
+rlb_status rlb_destroy(rlb_lattice* L) {
+  if (!L) return RLB_ERR_INVALID_ARG;
+  drop_graph(L);
+  delete L;
+  return RLB_OK;
+}
+
+rlb_status rlb_workspace_size(const rlb_lattice* L, size_t* bytes) {
+  if (!L || !bytes) return RLB_ERR_INVALID_ARG;
+  *bytes = L->total;
+  return RLB_OK;
+}
+
+rlb_status rlb_bind(rlb_lattice* L, void* workspace, size_t bytes, void* hip_stream) {
+  if (!L) return RLB_ERR_INVALID_ARG;
+  if (!workspace) return fail(L, RLB_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(workspace) % 256) return fail(L, RLB_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  if (bytes < L->total) return fail(L, RLB_ERR_INVALID_ARG, "workspace too small (see rlb_workspace_size)");
+  drop_graph(L);
+  L->ws = static_cast<char*>(workspace);
+  L->ws_bytes = bytes;
+  L->stream = static_cast<hipStream_t>(hip_stream);
+  L->initialised = false;
+  rlb_status st;
+  if ((st = upload(L, L->off_tubes, L->tubes.data(), L->tubes.size() * sizeof(TubeDev))) != RLB_OK) return st;
+  if (L->prec == RLB_FP32) {
+    if ((st = upload(L, L->off_jtab, L->jtab_f.data(), L->jtab_f.size() * 4)) != RLB_OK) return st;
+    if ((st = upload(L, L->off_aux, L->aux_f.data(), L->aux_f.size() * 4)) != RLB_OK) return st;
+  } else {
+    if ((st = upload(L, L->off_jtab, L->jtab_d.data(), L->jtab_d.size() * 8)) != RLB_OK) return st;
+    if ((st = upload(L, L->off_aux, L->aux_d.data(), L->aux_d.size() * 8)) != RLB_OK) return st;
+  }
+  if ((st = upload(L, L->off_itab, L->itab.data(), L->itab.size() * 8)) != RLB_OK) return st;
+  if ((st = upload(L, L->off_items, L->items.data(), L->items.size() * sizeof(WorkItem))) != RLB_OK) return st;
+  HIP_TRY(L, hipMemsetAsync(L->ws + L->off_flag, 0, 16, L->stream));
+  HIP_TRY(L, hipStreamSynchronize(L->stream));
+  return RLB_OK;
+}
+
+rlb_status rlb_set_stream(rlb_lattice* L, void* hip_stream) {
+  if (!L) return RLB_ERR_INVALID_ARG;
+  L->stream = static_cast<hipStream_t>(hip_stream);
+  return RLB_OK;
+}
+
+rlb_status rlb_set_schedule(rlb_lattice* L, const rlb_schedule* s) {
+  if (!L || !s) return RLB_ERR_INVALID_ARG;
+  if (s->tile != 128 && s->tile != 256) return fail(L, RLB_ERR_INVALID_ARG, "tile must be 128 or 256");
+  if (s->persistent != 0 && s->persistent != 1) return fail(L, RLB_ERR_INVALID_ARG, "persistent must be 0 or 1");
+  if (s->blocks_per_cu < 1 || s->blocks_per_cu > 64) return fail(L, RLB_ERR_INVALID_ARG, "blocks_per_cu in [1, 64]");
+  if (s->graph_steps < 0 || s->graph_steps > 4096) return fail(L, RLB_ERR_INVALID_ARG, "graph_steps in [0, 4096]");
+  const bool new_items = s->tile != L->sched.tile;
+  L->sched = *s;
+  drop_graph(L);
+  if (new_items) {
+    build_items(L);
+    if (L->ws) return upload(L, L->off_items, L->items.data(), L->items.size() * sizeof(WorkItem));
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_get_schedule(const rlb_lattice* L, rlb_schedule* s) {
+  if (!L || !s) return RLB_ERR_INVALID_ARG;
+  *s = L->sched;
+  return RLB_OK;
+}
+
+namespace {
+
+bool good_state(const rlb_state& s) {
+  return s.P > 0 && s.n > 0 && std::isfinite(s.P) && std::isfinite(s.n) && std::isfinite(s.u);
+}
+
+rlb_status launch_init_all(rlb_lattice* L) {
+  rlb_status st;
+  if ((st = upload(L, L->off_sides, L->sides_h.data(), L->sides_h.size() * 8)) != RLB_OK) return st;
+  if ((st = upload(L, L->off_mask, L->mask_h.data(), L->mask_h.size() * 4)) != RLB_OK) return st;
+  const bool fp32 = L->prec == RLB_FP32;
+  for (const Group& g : L->groups) {
+    LaunchShape ls = shape(L, g);
+    hipError_t e;
+    if (fp32) {
+      InitArgs<float> a;
+      a.tubes = L->dev<TubeDev>(L->off_tubes);
+      a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
+      a.nitems = g.item_end - g.item_begin;
+      a.aux_pairs = L->aux_pairs;
+      a.jtab = L->dev<float>(L->off_jtab);
+      a.itab = L->dev<double>(L->off_itab);
+      a.aux = L->dev<float>(L->off_aux);
+      a.sides = L->dev<double>(L->off_sides);
+      a.tube_mask = L->dev<int32_t>(L->off_mask);
+      a.f = L->dev<float>(L->off_F[0]);
+      a.rec = L->dev<double>(L->off_rec[0]);
+      a.flag = L->dev<unsigned>(L->off_flag);
+      e = launch_init(1, g.qpt, g.nvt, ls, &a, L->stream);
+    } else {
+      InitArgs<double> a;
+      a.tubes = L->dev<TubeDev>(L->off_tubes);
+      a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
+      a.nitems = g.item_end - g.item_begin;
+      a.aux_pairs = L->aux_pairs;
+      a.jtab = L->dev<double>(L->off_jtab);
+      a.itab = L->dev<double>(L->off_itab);
+      a.aux = L->dev<double>(L->off_aux);
+      a.sides = L->dev<double>(L->off_sides);
+      a.tube_mask = L->dev<int32_t>(L->off_mask);
+      a.f = L->dev<double>(L->off_F[0]);
+      a.rec = L->dev<double>(L->off_rec[0]);
+      a.flag = L->dev<unsigned>(L->off_flag);
+      e = launch_init(0, g.qpt, g.nvt, ls, &a, L->stream);
+    }
+    if (e != hipSuccess) return hip_fail(L, e, "init kernel launch");
+  }
+  return RLB_OK;
+}
+
+}  // namespace
+
+rlb_status rlb_set_initial_state(rlb_lattice* L, int32_t tube, rlb_state left, rlb_state right) {
+  rlb_status st = need_ready(L, false);
+  if (st != RLB_OK) return st;
+  if (tube != -1 && !check_tube(L, tube)) return fail(L, RLB_ERR_INVALID_ARG, "tube index out of range");
+  if (!good_state(left) || !good_state(right))
+    return fail(L, RLB_ERR_INVALID_ARG, "initial states need P > 0, n > 0 and finite u");
+  if (!L->initialised && tube != -1) return fail(L, RLB_ERR_STATE, "the first initial state must set every tube (tube = -1)");
+  for (int t = 0; t < L->ntubes; ++t) {
+    const bool on = tube == -1 || t == tube;
+    L->mask_h[t] = on ? 1 : 0;
+    if (on) {
+      double* s = &L->sides_h[6 * size_t(t)];
+      s[0] = left.P; s[1] = left.n; s[2] = left.u;
+      s[3] = right.P; s[4] = right.n; s[5] = right.u;
+      L->time[t] = 0.0;
+    }
+  }
+  if ((st = launch_init_all(L)) != RLB_OK) return st;
+  if (tube == -1) HIP_TRY(L, hipMemsetAsync(L->ws + L->off_flag, 0, 16, L->stream));
+  L->initialised = true;
+  return RLB_OK;
+}
+
+rlb_status rlb_set_initial_states(rlb_lattice* L, int32_t ntubes, const rlb_state* left, const rlb_state* right) {
+  rlb_status st = need_ready(L, false);
+  if (st != RLB_OK) return st;
+  if (ntubes != L->ntubes || !left || !right) return fail(L, RLB_ERR_INVALID_ARG, "need one left/right state per tube");
+  for (int t = 0; t < ntubes; ++t)
+    if (!good_state(left[t]) || !good_state(right[t]))
+      return fail(L, RLB_ERR_INVALID_ARG, "initial states need P > 0, n > 0 and finite u");
+  for (int t = 0; t < ntubes; ++t) {
+    L->mask_h[t] = 1;
+    double* s = &L->sides_h[6 * size_t(t)];
+    s[0] = left[t].P; s[1] = left[t].n; s[2] = left[t].u;
+    s[3] = right[t].P; s[4] = right[t].n; s[5] = right[t].u;
+    L->time[t] = 0.0;
+  }
+  if ((st = launch_init_all(L)) != RLB_OK) return st;
+  HIP_TRY(L, hipMemsetAsync(L->ws + L->off_flag, 0, 16, L->stream));
+  L->initialised = true;
+  return RLB_OK;
+}
+
+rlb_status rlb_step(rlb_lattice* L, int64_t nsteps) {
+  rlb_status st = need_ready(L, true);
+  if (st != RLB_OK) return st;
+  if (nsteps < 0) return fail(L, RLB_ERR_INVALID_ARG, "nsteps must be >= 0");
+  int64_t done = 0;
+  if (L->sched.graph_steps > 0 && nsteps >= L->sched.graph_steps) {
+    if ((st = ensure_graph(L)) != RLB_OK) return st;
+    for (; done + L->graph_steps <= nsteps; done += L->graph_steps)
+      HIP_TRY(L, hipGraphLaunch(L->graph_exec, L->stream));
+  }
+  if ((st = enqueue_steps(L, L->stream, nsteps - done)) != RLB_OK) return st;
+  for (int t = 0; t < L->ntubes; ++t) L->time[t] += nsteps * L->tubes[t].dt;
+  return RLB_OK;
+}
+
+rlb_status rlb_fields(rlb_lattice* L, int32_t tube, double* dev_out, int64_t ld) {
+  rlb_status st = need_ready(L, true);
+  if (st != RLB_OK) return st;
+  if (!check_tube(L, tube)) return fail(L, RLB_ERR_INVALID_ARG, "tube index out of range");
+  if (!dev_out || ld < L->tubes[tube].nx) return fail(L, RLB_ERR_INVALID_ARG, "need dev_out and ld >= nx");
+  hipError_t e = launch_fields(L->dev<TubeDev>(L->off_tubes), tube, L->tubes[tube].nx, L->dev<double>(L->off_rec[0]),
+                               dev_out, ld, L->dev<unsigned>(L->off_flag), L->stream);
+  if (e != hipSuccess) return hip_fail(L, e, "fields kernel launch");
+  return RLB_OK;
+}
+
+rlb_status rlb_moments(rlb_lattice* L, int32_t tube, double* host_out, int64_t ld) {
+  rlb_status st = need_ready(L, true);
+  if (st != RLB_OK) return st;
+  if (!check_tube(L, tube)) return fail(L, RLB_ERR_INVALID_ARG, "tube index out of range");
+  const int nx = L->tubes[tube].nx;
+  if (!host_out || ld < nx) return fail(L, RLB_ERR_INVALID_ARG, "need host_out and ld >= nx");
+  double* scratch = L->dev<double>(L->off_fields);
+  if ((st = rlb_fields(L, tube, scratch, nx)) != RLB_OK) return st;
+  HIP_TRY(L, hipMemcpy2DAsync(host_out, ld * 8, scratch, size_t(nx) * 8, size_t(nx) * 8, 10, hipMemcpyDeviceToHost,
+                              L->stream));
+  HIP_TRY(L, hipStreamSynchronize(L->stream));
+  return read_flag(L);
+}
+
+rlb_status rlb_totals(rlb_lattice* L, int32_t tube, double out[3]) {
+  rlb_status st = need_ready(L, true);
+  if (st != RLB_OK) return st;
+  if (!check_tube(L, tube) || !out) return fail(L, RLB_ERR_INVALID_ARG, "bad tube or out");
+  double* d = L->dev<double>(L->off_totals);
+  hipError_t e = launch_totals(L->dev<TubeDev>(L->off_tubes), tube, L->dev<double>(L->off_rec[0]), d, L->stream);
+  if (e != hipSuccess) return hip_fail(L, e, "totals kernel launch");
+  HIP_TRY(L, hipMemcpyAsync(out, d, 3 * 8, hipMemcpyDeviceToHost, L->stream));
+  HIP_TRY(L, hipStreamSynchronize(L->stream));
+  return read_flag(L);
+}
+
+rlb_status rlb_check(rlb_lattice* L) {
+  rlb_status st = need_ready(L, false);
+  if (st != RLB_OK) return st;
+  return read_flag(L);
+}
+
+rlb_status rlb_state_elems(const rlb_lattice* L, int64_t* elems) {
+  if (!L || !elems) return RLB_ERR_INVALID_ARG;
+  *elems = L->state_elems;
+  return RLB_OK;
+}
+
+rlb_status rlb_state_layout(const rlb_lattice* L, int32_t tube, int64_t* off, int64_t* ld) {
+  if (!L || !off || !ld || !check_tube(L, tube)) return RLB_ERR_INVALID_ARG;
+  *off = L->tubes[tube].f_off;
+  *ld = L->tubes[tube].ldx;
+  return RLB_OK;
+}
+
+rlb_status rlb_get_state(rlb_lattice* L, void* dst) {
+  rlb_status st = need_ready(L, true);
+  if (st != RLB_OK) return st;
+  if (!dst) return fail(L, RLB_ERR_INVALID_ARG, "dst is NULL");
+  hipError_t e = launch_copy(dst, L->ws + L->off_F[0], L->state_elems * L->rsize, L->stream);
+  if (e != hipSuccess) return hip_fail(L, e, "state copy");
+  return RLB_OK;
+}
+
+rlb_status rlb_set_state(rlb_lattice* L, const void* src) {
+  rlb_status st = need_ready(L, false);
+  if (st != RLB_OK) return st;
+  if (!src) return fail(L, RLB_ERR_INVALID_ARG, "src is NULL");
+  hipError_t e = launch_copy(L->ws + L->off_F[0], src, L->state_elems * L->rsize, L->stream);
+  if (e != hipSuccess) return hip_fail(L, e, "state copy");
+  const bool fp32 = L->prec == RLB_FP32;
+  e = launch_moments(fp32 ? 1 : 0, L->dev<TubeDev>(L->off_tubes), L->dev<WorkItem>(L->off_items),
+                     static_cast<int>(L->items.size()), L->sched.tile, L->ws + L->off_jtab,
+                     L->dev<double>(L->off_itab), L->ws + L->off_F[0], L->dev<double>(L->off_rec[0]), L->stream);
+  if (e != hipSuccess) return hip_fail(L, e, "moments kernel launch");
+  L->initialised = true;
+  return RLB_OK;
+}
+
+rlb_status rlb_set_tau(rlb_lattice* L, int32_t tube, double tau) {
+  if (!L || !check_tube(L, tube)) return RLB_ERR_INVALID_ARG;
+  rlb_tube_desc d = L->desc[tube];
+  d.tau = tau;
+  d.dt = L->tubes[tube].dt;  // the time step stays fixed
+  std::string msg;
+  rlb_status st = validate(d, tube, msg);
+  if (st != RLB_OK) return fail(L, st, msg);
+  L->desc[tube].tau = tau;
+  L->tubes[tube].tau_inv = 1.0 / tau;
+  if (L->ws) return upload(L, L->off_tubes + tube * sizeof(TubeDev), &L->tubes[tube], sizeof(TubeDev));
+  return RLB_OK;
+}
+
+rlb_status rlb_tube_info(const rlb_lattice* L, int32_t tube, double* dt, double* time, int32_t* Q) {
+  if (!L || !check_tube(L, tube)) return RLB_ERR_INVALID_ARG;
+  if (dt) *dt = L->tubes[tube].dt;
+  if (time) *time = L->time[tube];
+  if (Q) *Q = L->tubes[tube].qx * L->tubes[tube].qp;
+  return RLB_OK;
+}
+
+rlb_status rlb_tables(const rlb_lattice* L, int32_t tube, double* xi, double* w_xi, double* p, double* w_p) {
+  if (!L || !check_tube(L, tube)) return RLB_ERR_INVALID_ARG;
+  if (xi) std::copy(L->xi[tube].begin(), L->xi[tube].end(), xi);
+  if (w_xi) std::copy(L->wxi[tube].begin(), L->wxi[tube].end(), w_xi);
+  if (p) std::copy(L->p[tube].begin(), L->p[tube].end(), p);
+  if (w_p) std::copy(L->wp[tube].begin(), L->wp[tube].end(), w_p);
+  return RLB_OK;
+}
+
+rlb_status rlb_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
+  if ((!dst || !src) && bytes) return RLB_ERR_INVALID_ARG;
+  if ((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16) return RLB_ERR_INVALID_ARG;
+  hipError_t e = launch_copy(dst, src, bytes, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? RLB_OK : RLB_ERR_HIP;
+}
+
+const char* rlb_status_string(rlb_status st) {
+  switch (st) {
+    case RLB_OK: return "ok";
+    case RLB_ERR_INVALID_ARG: return "invalid argument";
+    case RLB_ERR_NONPHYSICAL: return "non-physical state";
+    case RLB_ERR_HIP: return "HIP runtime error";
+    case RLB_ERR_STATE: return "call out of order";
+    case RLB_ERR_UNSTABLE_DT: return "unstable time step";
+  }
+  return "unknown status";
+}
+
+const char* rlb_last_error(const rlb_lattice* L) {
+  if (!L) return g_create_error.c_str();
+  return L->err.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+// Internal data structures shared by the host library and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rlb {
+
+constexpr int kMaxQp = 8;   // radial (Gauss-Laguerre) order limit
+constexpr int kMaxNv = 7;   // angular truncation order limit
+constexpr int kMaxNp = 7;   // radial truncation order limit (n_p < q_p)
+
+// Polar-node table row (one per Gauss-Legendre node j of a tube):
+//   xi, w, w*xi, w*xi^2, P_0(xi) .. P_7(xi)
+constexpr int kJStride = 12;
+// Radial-node table row (one per Gauss-Laguerre node i of a tube):
+//   p, w_p, T0^3 w_p p, T0^4 w_p p^2, L_0(p) .. L_7(p)   (L = L^{(1)})
+constexpr int kIStride = 12;
+// Auxiliary angular rule used to project the equilibrium (symmetric pairs):
+//   xi_a > 0, then w_a (2k+1)/2 P_k(xi_a) for k = 0..7
+constexpr int kAuxStride = 10;
+constexpr int kAuxPairsFP64 = 24;  // 48-point Gauss-Legendre rule
+constexpr int kAuxPairsFP32 = 12;  // 24-point Gauss-Legendre rule
+
+// Sticky device flags.
+constexpr unsigned kFlagNonphysical = 1u;
+constexpr unsigned kFlagFastFlow = 2u;  // |v| > 0.95: projection rule less accurate
+
+struct TubeDev {
+  int64_t f_off;    // element offset of the tube in a state array
+  int64_t rec_off;  // double offset of the tube's moment record [5][ldx]
+  int32_t nx, ldx;  // cells, row stride (elements)
+  int32_t qx, qp, nv, np;
+  int32_t jrow, irow;  // first row of the tube in the polar / radial tables
+  double z_min, dz, dz_inv, dt, tau_inv, T0, weno_eps;
+  int32_t group;    // kernel instantiation group
+  int32_t pad;
+};
+
+// Work item of the stage kernels: a tile of cells of one tube.
+struct WorkItem {
+  int32_t tube;
+  int32_t x0;
+};
+
+template <typename Real>
+struct StageArgs {
+  const TubeDev* tubes;
+  const WorkItem* items;
+  int32_t nitems;
+  int32_t stage;       // 1, 2, 3 (SSP-RK3 stage)
+  int32_t aux_pairs;
+  const Real* jtab;
+  const double* itab;
+  const Real* aux;
+  const Real* fin;     // stage input
+  const Real* fn;      // state at the start of the step (stages 2, 3)
+  Real* fout;          // stage output (stage 3 may alias fn)
+  const double* rec_in;
+  double* rec_out;
+  unsigned* flag;
+};
+
+template <typename Real>
+struct InitArgs {
+  const TubeDev* tubes;
+  const WorkItem* items;
+  int32_t nitems;
+  int32_t aux_pairs;
+  const Real* jtab;
+  const double* itab;
+  const Real* aux;
+  const double* sides;  // per tube: P_L, n_L, u_L, P_R, n_R, u_R
+  const int32_t* tube_mask;  // per tube: 1 = initialise
+  Real* f;
+  double* rec;
+  unsigned* flag;
+};
+
+// Host-side launchers (defined in rlb_kernels.hip).
+struct LaunchShape {
+  int tile;
+  int grid;
+};
+hipError_t launch_stage(int prec_fp32, int qpt, int nvt, const LaunchShape& ls, const void* args,
+                        hipStream_t stream);
+hipError_t launch_init(int prec_fp32, int qpt, int nvt, const LaunchShape& ls, const void* args,
+                       hipStream_t stream);
+hipError_t launch_moments(int prec_fp32, const TubeDev* tubes, const WorkItem* items, int nitems, int tile,
+                          const void* jtab, const double* itab, const void* f, double* rec, hipStream_t stream);
+hipError_t launch_fields(const TubeDev* tubes, int tube, int nx, const double* rec, double* out, int64_t ld,
+                         unsigned* flag, hipStream_t stream);
+hipError_t launch_totals(const TubeDev* tubes, int tube, const double* rec, double* out, hipStream_t stream);
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
+}  // namespace rlb

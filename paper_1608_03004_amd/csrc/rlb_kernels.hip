@@ -1,0 +1,603 @@
+// HIP kernels for gfx950 (MI355X) of the relativistic lattice Boltzmann step
+// (Blaga & Ambrus, arXiv:1608.03004).
+//
+// Data layout in HBM: structure of arrays F[s][x] per tube (s = i*q_xi + j),
+// rows padded to a multiple of 64 elements so that a wavefront's 64 lanes
+// (one cell each) load and store whole, aligned cache lines.  Per-cell moment
+// records N0, Nz, T00, T0z, Tzz are FP64 arrays rec[5][x].
+//
+// One launch of `stage_kernel` is one SSP-RK3 stage for a list of (tube, tile)
+// work items.  Per work item, each lane owns one cell and:
+//   1. reads the FP64 moment record of the stage input (written by the
+//      previous stage's epilogue -- the moments cost no extra pass over F);
+//   2. solves the Landau matching in FP64;
+//   3. projects the Maxwell-Juettner equilibrium onto the truncated basis with
+//      an auxiliary Gauss-Legendre rule (coefficients D[i][k] in registers);
+//   4. streams over the quadrature points in chunks of CJ points: the chunk's
+//      F values of the tile plus a 3-cell halo go to LDS, each lane computes the
+//      WENO5 value at its cell's left face (the tile's last face by CJ extra
+//      lanes), then each lane forms advection + Anderson-Witting relaxation,
+//      the RK combination, stores the result and accumulates the five moments
+//      of the output (Kahan-compensated in FP32);
+//   5. writes the output moment record.
+// The outflow boundary (zero-gradient ghosts) is index clamping at load time.
+#include <hip/hip_runtime.h>
+
+#include "rlb_internal.h"
+
+namespace rlb {
+namespace {
+
+constexpr int kChunk = 8;  // quadrature points staged in LDS per barrier round
+
+// Read-only kernel inputs (tube descriptors, work lists, quadrature tables) are
+// read through the constant address space so that wave-uniform reads become
+// scalar loads into SGPRs instead of 64-lane vector loads.
+template <typename T>
+using cptr = __attribute__((address_space(4))) const T*;
+template <typename T>
+__device__ inline cptr<T> as_const(const T* p) {
+  return (cptr<T>)(p);
+}
+
+// n/d with one hardware reciprocal: FP32 takes one correction step (< 2 ulp);
+// FP64 refines the reciprocal twice by Newton's method and corrects the
+// quotient once, which is close to correctly rounded.
+__device__ inline float fast_div(float n, float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  const float q = n * r;
+  return fmaf(r, fmaf(-d, q, n), q);
+}
+__device__ inline double fast_div(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  const double q = n * r;
+  return fma(r, fma(-d, q, n), q);
+}
+
+// ---------------------------------------------------------------------------
+// Small arithmetic helpers
+// ---------------------------------------------------------------------------
+template <typename Real>
+struct Acc;  // moment accumulator over the polar nodes of one radial node
+
+template <>
+struct Acc<double> {
+  double s = 0.0;
+  __device__ void add(double x) { s += x; }
+  __device__ double value() const { return s; }
+};
+
+// Kahan-compensated FP32 sum.
+template <>
+struct Acc<float> {
+  float s = 0.0f, c = 0.0f;
+  __device__ void add(float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ double value() const { return double(s) - double(c); }
+};
+
+struct Macro {
+  double e, v, gamma, u, n, T;
+  bool ok;
+};
+
+// Landau matching T^mu_nu u^nu = -e u^mu for the 1D moments
+// m = (N0, Nz, T00, T0z, Tzz) (section Relativistic LB equation).  The 2x2
+// eigenproblem in the t-z block gives e = (T00 - Tzz + D)/2 and
+// v = 2 T0z / (T00 + Tzz + D) with D^2 = (T00+Tzz)^2 - 4 T0z^2; the density is
+// n = -u_mu N^mu and the temperature T = e/(3n) (massless gas, e = 3P = 3nT).
+__device__ inline Macro landau(const double m[5]) {
+  Macro M;
+  const double a = m[2] + m[4];
+  const double disc = (a - 2.0 * m[3]) * (a + 2.0 * m[3]);
+  const double D = sqrt(disc);
+  M.e = 0.5 * (m[2] - m[4] + D);
+  M.v = 2.0 * m[3] / (a + D);
+  M.gamma = 1.0 / sqrt((1.0 - M.v) * (1.0 + M.v));
+  M.u = M.gamma * M.v;
+  M.n = M.gamma * (m[0] - M.v * m[1]);
+  M.T = M.e / (3.0 * M.n);
+  M.ok = (disc >= 0.0) && (M.e > 0.0) && (M.n > 0.0) && (fabs(M.v) < 1.0) && isfinite(M.T);
+  return M;
+}
+
+// Coefficients of the truncated equilibrium at the radial nodes:
+//   F_eq(p_i, xi) = sum_{k<=n_v} D[i][k] P_k(xi),
+//   D[i][k] = (2k+1)/2 int_{-1}^{1} P_k(xi) G_i(xi) dxi,
+//   G_i(xi) = n/(4 T T0^2) y^2 sum_{l<=n_p} L_l(p_i) (1 - (T/T0) y)^l,
+//   y = 1/(gamma - xi u),
+// which is the orthogonal projection of eq. feqtrunc (the Laplace transform of
+// the Laguerre polynomials done in closed form, the xi integral by a symmetric
+// auxiliary Gauss-Legendre rule whose node pairs +-xi_a share one pass).
+template <typename Real, int QPT, int NVT>
+__device__ inline void feq_coefficients(Real n, Real T, Real gamma, Real u, Real T0, int qp, int np, int nv,
+                                        cptr<double> itab, cptr<Real> aux,
+                                        int aux_pairs, Real D[QPT][NVT + 1]) {
+#pragma unroll
+  for (int i = 0; i < QPT; ++i)
+#pragma unroll
+    for (int k = 0; k <= NVT; ++k) D[i][k] = Real(0);
+  const Real r = T / T0;
+  for (int a = 0; a < aux_pairs; ++a) {
+    cptr<Real> A = aux + a * kAuxStride;
+    const Real xa = A[0];
+    const Real yp = fast_div(Real(1), gamma - xa * u);
+    const Real ym = fast_div(Real(1), gamma + xa * u);
+    const Real qp_ = Real(1) - r * yp, qm = Real(1) - r * ym;
+    const Real yp2 = yp * yp, ym2 = ym * ym;
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+      if (i < qp) {
+        cptr<double> L = itab + i * kIStride + 4;
+        Real sp = Real(L[np]), sm = Real(L[np]);
+        for (int l = np - 1; l >= 0; --l) {
+          sp = sp * qp_ + Real(L[l]);
+          sm = sm * qm + Real(L[l]);
+        }
+        const Real gp = yp2 * sp, gm = ym2 * sm;
+        const Real ev = gp + gm, od = gp - gm;
+#pragma unroll
+        for (int k = 0; k <= NVT; ++k) D[i][k] += A[1 + k] * ((k & 1) ? od : ev);
+      }
+    }
+  }
+  const Real pref = n / (Real(4) * T * T0 * T0);
+#pragma unroll
+  for (int i = 0; i < QPT; ++i)
+#pragma unroll
+    for (int k = 0; k <= NVT; ++k) D[i][k] = (k <= nv) ? D[i][k] * pref : Real(0);
+}
+
+// Fifth-order WENO (Jiang-Shu) value at the face between v3 and v4 from the
+// upwind-ordered values v1..v5.  The three nonlinear weights
+// alpha_r = d_r/(eps+beta_r)^2 are normalised with a single division by
+// multiplying numerator and denominator by prod_r (eps+beta_r)^2.
+template <typename Real>
+__device__ inline Real weno5(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps) {
+  const Real q0 = (Real(2) * v1 - Real(7) * v2 + Real(11) * v3) * Real(1.0 / 6.0);
+  const Real q1 = (-v2 + Real(5) * v3 + Real(2) * v4) * Real(1.0 / 6.0);
+  const Real q2 = (Real(2) * v3 + Real(5) * v4 - v5) * Real(1.0 / 6.0);
+  const Real t0 = v1 - Real(2) * v2 + v3, s0 = v1 - Real(4) * v2 + Real(3) * v3;
+  const Real t1 = v2 - Real(2) * v3 + v4, s1 = v2 - v4;
+  const Real t2 = v3 - Real(2) * v4 + v5, s2 = Real(3) * v3 - Real(4) * v4 + v5;
+  const Real c13 = Real(13.0 / 12.0), c14 = Real(0.25);
+  const Real e0 = eps + c13 * t0 * t0 + c14 * s0 * s0;
+  const Real e1 = eps + c13 * t1 * t1 + c14 * s1 * s1;
+  const Real e2 = eps + c13 * t2 * t2 + c14 * s2 * s2;
+  const Real A = e0 * e0, B = e1 * e1, C = e2 * e2;
+  const Real a0 = Real(0.1) * (B * C), a1 = Real(0.6) * (A * C), a2 = Real(0.3) * (A * B);
+  return fast_div(a0 * q0 + a1 * q1 + a2 * q2, a0 + a1 + a2);
+}
+
+// WENO value at the face between tile positions k+2 and k+3 (left face of the
+// cell stored at k+3), upwinded by the sign of xi.
+template <typename Real>
+__device__ inline Real face_value(const Real* row, int k, bool positive, Real eps) {
+  if (positive) return weno5(row[k], row[k + 1], row[k + 2], row[k + 3], row[k + 4], eps);
+  return weno5(row[k + 5], row[k + 4], row[k + 3], row[k + 2], row[k + 1], eps);
+}
+
+__device__ inline void raise_flag(unsigned* flag, unsigned bits) { atomicOr(flag, bits); }
+
+template <typename Real>
+__device__ inline void load_record(const double* rec, int64_t ldx, int x, double m[5]) {
+#pragma unroll
+  for (int c = 0; c < 5; ++c) m[c] = rec[c * ldx + x];
+}
+
+// ---------------------------------------------------------------------------
+// Stage kernel
+// ---------------------------------------------------------------------------
+// Loads of one chunk: the tile's own cells for kChunk points (rows clamped to
+// the last valid point, so every lane always issues the same loads) and, in
+// wave 0, the 6-cell halo of all kChunk points with one instruction.
+template <typename Real, int TILE>
+struct ChunkLoads {
+  Real f[kChunk];
+  Real halo;
+};
+
+template <typename Real, int TILE>
+__device__ inline void issue_chunk(const Real* fin, int64_t ldx, int qx, int i, int j0, int xc, int t, int x0,
+                                   int nx, ChunkLoads<Real, TILE>& L) {
+#pragma unroll
+  for (int c = 0; c < kChunk; ++c) {
+    const int j = min(j0 + c, qx - 1);
+    const Real* row = fin + int64_t(i * qx + j) * ldx;
+    L.f[c] = row[xc];
+  }
+  if (t < 64) {  // wave 0: lane h + 6c loads halo cell h of chunk point c
+    const int c = min(t / 6, kChunk - 1), h = t % 6;
+    const int j = min(j0 + c, qx - 1);
+    const int hx = h < 3 ? max(x0 - 3 + h, 0) : min(x0 + TILE + (h - 3), nx - 1);
+    L.halo = fin[int64_t(i * qx + j) * ldx + hx];
+  }
+}
+
+template <typename Real, int TILE, int QPT, int NVT, bool HAS_FN>
+__global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
+  __shared__ Real tile[kChunk][TILE + 6];
+  __shared__ Real faces[kChunk][TILE + 1];
+  const int t = threadIdx.x;
+  const cptr<WorkItem> items = as_const(a.items);
+  const cptr<TubeDev> tubes = as_const(a.tubes);
+  for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    const int wtube = items[item].tube, wx0 = items[item].x0;
+    const cptr<TubeDev> tbp = tubes + wtube;
+    const int nx = tbp->nx, qx = tbp->qx, qp = tbp->qp;
+    const int64_t ldx = tbp->ldx;
+    const int x0 = wx0;
+    const int x = x0 + t;
+    const bool valid = x < nx;
+    const int xc = valid ? x : nx - 1;
+    const int64_t f_off = tbp->f_off;
+    const Real* fin = a.fin + f_off;
+    const Real* fn = a.fn + f_off;
+    Real* fout = a.fout + f_off;
+    const cptr<Real> jtab = as_const(a.jtab) + int64_t(tbp->jrow) * kJStride;
+    const cptr<double> itab = as_const(a.itab) + int64_t(tbp->irow) * kIStride;
+
+    // first chunk's loads go out before the per-cell prologue
+    const int nci = (qx + kChunk - 1) / kChunk;
+    const int nchunks = qp * nci;
+    ChunkLoads<Real, TILE> cur;
+    issue_chunk<Real, TILE>(fin, ldx, qx, 0, 0, xc, t, x0, nx, cur);
+
+    // 1-2. moments of the stage input -> Landau frame (FP64)
+    double m[5];
+    const double* rin = a.rec_in + tbp->rec_off;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) m[c] = rin[c * ldx + xc];
+    const Macro M = landau(m);
+    if (valid && !M.ok) raise_flag(a.flag, kFlagNonphysical);
+    if (valid && fabs(M.v) > 0.95) raise_flag(a.flag, kFlagFastFlow);
+
+    // 3. equilibrium coefficients and relaxation rate (gamma - xi u)/tau
+    Real D[QPT][NVT + 1];
+    feq_coefficients<Real, QPT, NVT>(Real(M.n), Real(M.T), Real(M.gamma), Real(M.u), Real(tbp->T0), qp, tbp->np,
+                                     tbp->nv, itab, as_const(a.aux), a.aux_pairs, D);
+    const double tau_inv = tbp->tau_inv;
+    const Real g0 = Real(M.gamma * tau_inv), g1 = Real(M.u * tau_inv);
+    const Real dt = Real(tbp->dt), dz_inv = Real(tbp->dz_inv), eps = Real(tbp->weno_eps);
+    const int stage = a.stage;
+    const Real cn = stage == 1 ? Real(0) : (stage == 2 ? Real(0.75) : Real(1.0 / 3.0));
+    const Real cs = stage == 1 ? Real(1) : (stage == 2 ? Real(0.25) : Real(2.0 / 3.0));
+
+    double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    Acc<Real> acc0, acc1, acc2;
+    for (int k = 0; k < nchunks; ++k) {
+      const int i = k / nci;
+      const int j0 = (k - i * nci) * kChunk;
+      const int cj = min(kChunk, qx - j0);
+      // prefetch the next chunk (the last chunk re-loads itself)
+      ChunkLoads<Real, TILE> nxt;
+      {
+        const int kn = min(k + 1, nchunks - 1);
+        const int in = kn / nci;
+        issue_chunk<Real, TILE>(fin, ldx, qx, in, (kn - in * nci) * kChunk, xc, t, x0, nx, nxt);
+      }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) tile[c][t + 3] = cur.f[c];
+      if (t < 6 * kChunk) {
+        const int c = t / 6, h = t % 6;
+        tile[c][h < 3 ? h : TILE + h] = cur.halo;
+      }
+      __syncthreads();
+      // f^n of this chunk, consumed after the faces
+      Real nr[kChunk];
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        if (HAS_FN) {
+          const int j = min(j0 + c, qx - 1);
+          nr[c] = fn[int64_t(i * qx + j) * ldx + xc];
+        } else {
+          nr[c] = Real(0);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        const bool pos = jtab[min(j0 + c, qx - 1) * kJStride] >= Real(0);
+        faces[c][t] = face_value(tile[c], t, pos, eps);
+      }
+      if (t < kChunk) {  // the tile's right-most face, one chunk point per lane
+        const bool pos = jtab[min(j0 + t, qx - 1) * kJStride] >= Real(0);
+        faces[t][TILE] = face_value(tile[t], TILE, pos, eps);
+      }
+      __syncthreads();
+      // coefficients of this radial node
+      Real d[NVT + 1];
+#pragma unroll
+      for (int kk = 0; kk <= NVT; ++kk) {
+        d[kk] = D[0][kk];
+#pragma unroll
+        for (int ii = 1; ii < QPT; ++ii)
+          if (ii == i) d[kk] = D[ii][kk];
+      }
+#pragma unroll
+      for (int c = 0; c < kChunk; ++c) {
+        if (c < cj) {
+          const cptr<Real> J = jtab + (j0 + c) * kJStride;
+          const Real xi = J[0];
+          Real feq = Real(0);
+#pragma unroll
+          for (int kk = 0; kk <= NVT; ++kk) feq += d[kk] * J[4 + kk];
+          const Real adv = -xi * dz_inv * (faces[c][t + 1] - faces[c][t]);
+          const Real rate = g0 - xi * g1;
+          const Real fr = cur.f[c];
+          const Real L = adv - rate * (fr - feq);
+          const Real out = HAS_FN ? cn * nr[c] + cs * (fr + dt * L) : fr + dt * L;
+          if (valid) fout[int64_t(i * qx + j0 + c) * ldx + x] = out;
+          acc0.add(J[1] * out);
+          acc1.add(J[2] * out);
+          acc2.add(J[3] * out);
+        }
+      }
+      if (j0 + kChunk >= qx) {  // last chunk of radial node i: fold its sums
+        const cptr<double> I = itab + i * kIStride;
+        const double s0 = acc0.value(), s1 = acc1.value(), s2 = acc2.value();
+        mom[0] += I[2] * s0;
+        mom[1] += I[2] * s1;
+        mom[2] += I[3] * s0;
+        mom[3] += I[3] * s1;
+        mom[4] += I[3] * s2;
+        acc0 = Acc<Real>();
+        acc1 = Acc<Real>();
+        acc2 = Acc<Real>();
+      }
+      __syncthreads();
+      cur = nxt;
+    }
+    if (valid) {
+      double* ro = a.rec_out + tbp->rec_off;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) ro[c * ldx + x] = mom[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Initial condition (eq. condinit): truncated equilibrium of the side state.
+// ---------------------------------------------------------------------------
+template <typename Real, int TILE, int QPT, int NVT>
+__global__ __launch_bounds__(TILE) void init_kernel(InitArgs<Real> a) {
+  const int t = threadIdx.x;
+  for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+    const WorkItem wi = a.items[item];
+    if (!a.tube_mask[wi.tube]) continue;
+    const TubeDev& tb = a.tubes[wi.tube];
+    const int x = wi.x0 + t;
+    if (x >= tb.nx) continue;
+    const double z = tb.z_min + (x + 0.5) * tb.dz;
+    const double* st = a.sides + 6 * wi.tube + (z < 0.0 ? 0 : 3);
+    const double P = st[0], n = st[1], u = st[2];
+    const double T = P / n, gamma = sqrt(1.0 + u * u);
+    const Real* jtab = a.jtab + int64_t(tb.jrow) * kJStride;
+    const double* itab = a.itab + int64_t(tb.irow) * kIStride;
+    Real D[QPT][NVT + 1];
+    feq_coefficients<Real, QPT, NVT>(Real(n), Real(T), Real(gamma), Real(u), Real(tb.T0), tb.qp, tb.np, tb.nv,
+                                     as_const(itab), as_const(a.aux), a.aux_pairs, D);
+    Real* f = a.f + tb.f_off;
+    double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+      if (i < tb.qp) {
+        Acc<Real> acc0, acc1, acc2;
+        for (int j = 0; j < tb.qx; ++j) {
+          const Real* J = jtab + j * kJStride;
+          Real F = Real(0);
+#pragma unroll
+          for (int k = 0; k <= NVT; ++k) F += D[i][k] * J[4 + k];
+          f[int64_t(i * tb.qx + j) * tb.ldx + x] = F;
+          acc0.add(J[1] * F);
+          acc1.add(J[2] * F);
+          acc2.add(J[3] * F);
+        }
+        const double* I = itab + i * kIStride;
+        const double a0 = acc0.value(), a1 = acc1.value(), a2 = acc2.value();
+        mom[0] += I[2] * a0;
+        mom[1] += I[2] * a1;
+        mom[2] += I[3] * a0;
+        mom[3] += I[3] * a1;
+        mom[4] += I[3] * a2;
+      }
+    }
+    double* rec = a.rec + tb.rec_off;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) rec[int64_t(c) * tb.ldx + x] = mom[c];
+  }
+}
+
+// Moment records of an arbitrary state (after rlb_set_state).
+template <typename Real>
+__global__ __launch_bounds__(256) void moments_kernel(const TubeDev* tubes, const WorkItem* items, int nitems,
+                                                      int tile, const Real* jtab_all, const double* itab_all,
+                                                      const Real* f_all, double* rec_all) {
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const WorkItem wi = items[item];
+    const TubeDev& tb = tubes[wi.tube];
+    for (int t = threadIdx.x; t < tile; t += blockDim.x) {
+      const int x = wi.x0 + t;
+      if (x >= tb.nx) continue;
+      const Real* jtab = jtab_all + int64_t(tb.jrow) * kJStride;
+      const double* itab = itab_all + int64_t(tb.irow) * kIStride;
+      const Real* f = f_all + tb.f_off;
+      double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < tb.qp; ++i) {
+        Acc<Real> acc0, acc1, acc2;
+        for (int j = 0; j < tb.qx; ++j) {
+          const Real* J = jtab + j * kJStride;
+          const Real F = f[int64_t(i * tb.qx + j) * tb.ldx + x];
+          acc0.add(J[1] * F);
+          acc1.add(J[2] * F);
+          acc2.add(J[3] * F);
+        }
+        const double* I = itab + i * kIStride;
+        const double a0 = acc0.value(), a1 = acc1.value(), a2 = acc2.value();
+        mom[0] += I[2] * a0;
+        mom[1] += I[2] * a1;
+        mom[2] += I[3] * a0;
+        mom[3] += I[3] * a1;
+        mom[4] += I[3] * a2;
+      }
+      double* rec = rec_all + tb.rec_off;
+      for (int c = 0; c < 5; ++c) rec[int64_t(c) * tb.ldx + x] = mom[c];
+    }
+  }
+}
+
+// Diagnostic fields from the moment record: N0..Tzz, e, n, v, T, |N|.
+__global__ __launch_bounds__(256) void fields_kernel(const TubeDev* tubes, int tube, const double* rec_all,
+                                                     double* out, int64_t ld, unsigned* flag) {
+  const TubeDev& tb = tubes[tube];
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= tb.nx) return;
+  double m[5];
+  const double* rec = rec_all + tb.rec_off;
+  for (int c = 0; c < 5; ++c) m[c] = rec[int64_t(c) * tb.ldx + x];
+  const Macro M = landau(m);
+  if (!M.ok) raise_flag(flag, kFlagNonphysical);
+  for (int c = 0; c < 5; ++c) out[c * ld + x] = m[c];
+  out[5 * ld + x] = M.e;
+  out[6 * ld + x] = M.n;
+  out[7 * ld + x] = M.v;
+  out[8 * ld + x] = M.T;
+  out[9 * ld + x] = sqrt((m[0] - m[1]) * (m[0] + m[1]));
+}
+
+// FP64 totals dz * sum_x {N0, T00, T0z} with a fixed-order tree reduction.
+__global__ __launch_bounds__(256) void totals_kernel(const TubeDev* tubes, int tube, const double* rec_all,
+                                                     double* out) {
+  __shared__ double red[3][256];
+  const TubeDev& tb = tubes[tube];
+  const double* rec = rec_all + tb.rec_off;
+  double s[3] = {0.0, 0.0, 0.0};
+  for (int x = threadIdx.x; x < tb.nx; x += blockDim.x) {
+    s[0] += rec[x];
+    s[1] += rec[2 * int64_t(tb.ldx) + x];
+    s[2] += rec[3 * int64_t(tb.ldx) + x];
+  }
+  for (int c = 0; c < 3; ++c) red[c][threadIdx.x] = s[c];
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int c = 0; c < 3; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 3; ++c) out[c] = red[c][0] * tb.dz;
+}
+
+// Plain streaming copy (16-byte vectors), for bandwidth calibration.
+__global__ __launch_bounds__(256) void copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
+                                                   size_t n16) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n16; k += stride) dst[k] = src[k];
+}
+
+template <typename Real, int TILE, int QPT, int NVT>
+hipError_t launch_stage_t(const LaunchShape& ls, const void* args, hipStream_t s) {
+  const StageArgs<Real>& a = *static_cast<const StageArgs<Real>*>(args);
+  if (a.stage == 1)
+    hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, false>), dim3(ls.grid), dim3(TILE), 0, s, a);
+  else
+    hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, true>), dim3(ls.grid), dim3(TILE), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename Real, int QPT, int NVT>
+hipError_t launch_stage_tile(const LaunchShape& ls, const void* args, hipStream_t s) {
+  switch (ls.tile) {
+    case 128: return launch_stage_t<Real, 128, QPT, NVT>(ls, args, s);
+    case 256: return launch_stage_t<Real, 256, QPT, NVT>(ls, args, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename Real>
+hipError_t launch_stage_real(int qpt, int nvt, const LaunchShape& ls, const void* args, hipStream_t s) {
+  if (qpt == 3 && nvt == 5) return launch_stage_tile<Real, 3, 5>(ls, args, s);
+  if (qpt == 4 && nvt == 5) return launch_stage_tile<Real, 4, 5>(ls, args, s);
+  if (qpt == 8 && nvt == 7) return launch_stage_tile<Real, 8, 7>(ls, args, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename Real, int QPT, int NVT>
+hipError_t launch_init_t(const LaunchShape& ls, const void* args, hipStream_t s) {
+  const InitArgs<Real>& a = *static_cast<const InitArgs<Real>*>(args);
+  if (ls.tile == 128) {
+    hipLaunchKernelGGL((init_kernel<Real, 128, QPT, NVT>), dim3(ls.grid), dim3(128), 0, s, a);
+  } else if (ls.tile == 256) {
+    hipLaunchKernelGGL((init_kernel<Real, 256, QPT, NVT>), dim3(ls.grid), dim3(256), 0, s, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t launch_init_real(int qpt, int nvt, const LaunchShape& ls, const void* args, hipStream_t s) {
+  if (qpt == 3 && nvt == 5) return launch_init_t<Real, 3, 5>(ls, args, s);
+  if (qpt == 4 && nvt == 5) return launch_init_t<Real, 4, 5>(ls, args, s);
+  if (qpt == 8 && nvt == 7) return launch_init_t<Real, 8, 7>(ls, args, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_stage(int prec_fp32, int qpt, int nvt, const LaunchShape& ls, const void* args,
+                        hipStream_t stream) {
+  return prec_fp32 ? launch_stage_real<float>(qpt, nvt, ls, args, stream)
+                   : launch_stage_real<double>(qpt, nvt, ls, args, stream);
+}
+
+hipError_t launch_init(int prec_fp32, int qpt, int nvt, const LaunchShape& ls, const void* args,
+                       hipStream_t stream) {
+  return prec_fp32 ? launch_init_real<float>(qpt, nvt, ls, args, stream)
+                   : launch_init_real<double>(qpt, nvt, ls, args, stream);
+}
+
+hipError_t launch_moments(int prec_fp32, const TubeDev* tubes, const WorkItem* items, int nitems, int tile,
+                          const void* jtab, const double* itab, const void* f, double* rec, hipStream_t stream) {
+  if (prec_fp32)
+    hipLaunchKernelGGL(moments_kernel<float>, dim3(nitems), dim3(256), 0, stream, tubes, items, nitems, tile,
+                       static_cast<const float*>(jtab), itab, static_cast<const float*>(f), rec);
+  else
+    hipLaunchKernelGGL(moments_kernel<double>, dim3(nitems), dim3(256), 0, stream, tubes, items, nitems, tile,
+                       static_cast<const double*>(jtab), itab, static_cast<const double*>(f), rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_fields(const TubeDev* tubes, int tube, int nx, const double* rec, double* out, int64_t ld,
+                         unsigned* flag, hipStream_t stream) {
+  hipLaunchKernelGGL(fields_kernel, dim3((nx + 255) / 256), dim3(256), 0, stream, tubes, tube, rec, out, ld, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_totals(const TubeDev* tubes, int tube, const double* rec, double* out, hipStream_t stream) {
+  hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(256), 0, stream, tubes, tube, rec, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream) {
+  const size_t n16 = bytes / 16;
+  const int grid = static_cast<int>(std::min<size_t>((n16 + 255) / 256, 256 * 64));
+  if (n16) {
+    hipLaunchKernelGGL(copy_kernel, dim3(grid), dim3(256), 0, stream, static_cast<uint4*>(dst),
+                       static_cast<const uint4*>(src), n16);
+  }
+  const size_t tail = bytes - n16 * 16;
+  if (tail) {
+    hipError_t e = hipMemcpyAsync(static_cast<char*>(dst) + n16 * 16, static_cast<const char*>(src) + n16 * 16, tail,
+                                  hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rlb

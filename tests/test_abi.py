@@ -1,0 +1,119 @@
+"""Host-side checks of the C interface: the library loads, exports every
+symbol include/rlb.h declares, validates arguments synchronously, and builds
+the same quadrature tables as the paper's formulas (through the oracle).
+No test here launches a kernel."""
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+from paper_1608_03004_amd import rlb
+from oracle import oracle as O
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return rlb.load_library()
+
+
+def _create(lib, tubes, prec=rlb.RLB_FP64):
+    arr = (rlb.TubeDesc * len(tubes))(*[t.c() for t in tubes])
+    h = ctypes.c_void_p()
+    st = lib.rlb_create(arr, len(tubes), prec, 0, ctypes.byref(h))
+    return st, h
+
+
+def test_every_declared_symbol_is_exported(lib):
+    declared = rlb.declared_symbols()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    bound = set(rlb._SIGNATURES) | set(rlb._STRING_FUNCS)
+    assert set(declared) == bound, set(declared) ^ bound
+
+
+def test_defaults_are_the_papers(lib):
+    d = rlb.TubeDesc()
+    assert lib.rlb_tube_defaults(ctypes.byref(d)) == 0
+    assert (d.nx, d.q_xi, d.q_p, d.n_v, d.n_p) == (800, 8, 3, 5, 2)
+    assert (d.z_min, d.z_max, d.cfl, d.T0) == (-0.5, 0.5, 0.5, 1.0)
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(nx=4), rlb.RLB_ERR_INVALID_ARG),
+    (dict(q_p=9), rlb.RLB_ERR_INVALID_ARG),
+    (dict(n_p=3, q_p=3), rlb.RLB_ERR_INVALID_ARG),
+    (dict(q_p=2, n_p=1, n_v=5, q_xi=2), rlb.RLB_ERR_INVALID_ARG),   # q_xi too small for T^{mu nu}
+    (dict(n_v=8), rlb.RLB_ERR_INVALID_ARG),
+    (dict(tau=0.0), rlb.RLB_ERR_INVALID_ARG),
+    (dict(tau=-1.0), rlb.RLB_ERR_INVALID_ARG),
+    (dict(T0=0.0), rlb.RLB_ERR_INVALID_ARG),
+    (dict(weno_eps=0.0), rlb.RLB_ERR_INVALID_ARG),
+    (dict(z_min=0.5, z_max=-0.5), rlb.RLB_ERR_INVALID_ARG),
+    (dict(dt=1e-2, nx=800), rlb.RLB_ERR_UNSTABLE_DT),               # dt/dz = 8
+    (dict(dt=5e-4, tau=1e-4, nx=800), rlb.RLB_ERR_UNSTABLE_DT),     # dt/tau = 5
+    (dict(dt_tau_max=5.0, tau=1e-4, cfl=0.5, nx=100), rlb.RLB_ERR_UNSTABLE_DT),
+])
+def test_invalid_descriptors_are_rejected(lib, bad, status):
+    st, h = _create(lib, [rlb.Tube(**bad)])
+    assert st == status
+    assert not h.value
+    assert lib.rlb_last_error(None)
+
+
+def test_valid_create_and_host_queries(lib):
+    tubes = [rlb.Tube(nx=800), rlb.Tube(nx=1000, q_xi=16, q_p=4, tau=math.inf), rlb.Tube(nx=77, q_xi=5, n_v=7, q_p=5, n_p=3)]
+    st, h = _create(lib, tubes)
+    assert st == 0 and h.value
+    size = ctypes.c_size_t()
+    assert lib.rlb_workspace_size(h, ctypes.byref(size)) == 0
+    n = ctypes.c_int64()
+    assert lib.rlb_state_elems(h, ctypes.byref(n)) == 0
+    expect = sum(t.Q * ((t.nx + 63) // 64 * 64) for t in tubes)
+    assert n.value == expect
+    assert size.value >= 3 * expect * 8
+    off, ld = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.rlb_state_layout(h, 1, ctypes.byref(off), ctypes.byref(ld)) == 0
+    assert off.value == 24 * 832 and ld.value == 1024
+    # calls that need a bound workspace fail cleanly
+    assert lib.rlb_step(h, 1) == rlb.RLB_ERR_STATE
+    assert lib.rlb_set_initial_state(h, -1, rlb.State(1, 1, 0), rlb.State(0.1, 0.125, 0)) == rlb.RLB_ERR_STATE
+    s = rlb.Schedule(100, 0, 4, 0)
+    assert lib.rlb_set_schedule(h, ctypes.byref(s)) == rlb.RLB_ERR_INVALID_ARG
+    s = rlb.Schedule(128, 1, 4, 8)
+    assert lib.rlb_set_schedule(h, ctypes.byref(s)) == 0
+    dt, t, Q = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    assert lib.rlb_tube_info(h, 0, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(Q)) == 0
+    assert abs(dt.value - 0.5 / 800) < 1e-18 and Q.value == 24
+    assert lib.rlb_tube_info(h, 3, None, None, None) == rlb.RLB_ERR_INVALID_ARG
+    assert lib.rlb_set_tau(h, 0, -1.0) == rlb.RLB_ERR_INVALID_ARG
+    assert lib.rlb_destroy(h) == 0
+
+
+@pytest.mark.parametrize("q_xi,q_p", [(2, 3), (5, 3), (8, 3), (64, 4), (128, 3), (200, 5), (256, 4)])
+def test_device_tables_match_the_oracle(lib, q_xi, q_p):
+    # Two independent constructions (Golub-Welsch with Christoffel weights here,
+    # Newton with the paper's weight formula in the oracle) agree to ~1 ulp.
+    n_p = min(2, q_p - 1)
+    n_v = min(5, 2 * q_xi - 3) if q_xi > 1 else 0
+    t = rlb.Tube(nx=16, q_xi=q_xi, q_p=q_p, n_p=max(n_p, 0), n_v=max(n_v, 0))
+    if q_p == 1:
+        t.n_p = 0
+    st, h = _create(lib, [t])
+    assert st == 0, lib.rlb_last_error(None)
+    xi, wxi, p, wp = (np.zeros(q_xi), np.zeros(q_xi), np.zeros(q_p), np.zeros(q_p))
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert lib.rlb_tables(h, 0, *(a.ctypes.data_as(dp) for a in (xi, wxi, p, wp))) == 0
+    oxi, owxi = O.gauss_legendre(q_xi)
+    op, owp = O.gauss_laguerre1(q_p)
+    assert np.abs(xi - oxi).max() <= 2.3e-16
+    assert np.abs(wxi / owxi - 1).max() <= 5e-16
+    assert np.abs(p / op - 1).max() <= 5e-16
+    assert np.abs(wp / owp - 1).max() <= 1e-15
+    lib.rlb_destroy(h)
+
+
+def test_status_strings(lib):
+    for st in range(0, -6, -1):
+        assert lib.rlb_status_string(st)
