@@ -545,7 +545,9 @@ int oracle_step_tangent(const oracle_tube* t, double* F, double* dF, double dtau
   const int64_t N = int64_t(tb.Q()) * t->nx;
   std::vector<Dual> G(N), G1(N), G2(N), L(N);
   for (int64_t a = 0; a < N; ++a) G[a] = Dual(F[a], dF[a]);
-  const Dual ti = Dual(1.0) / Dual(t->tau, dtau);
+  // d(1/tau) = -dtau/tau^2, written out so that tau = +inf (collisionless
+  // limit) gives an exact zero instead of 0 * inf in the quotient rule.
+  const Dual ti = Dual(1.0 / t->tau, -dtau / (t->tau * t->tau));
   for (int64_t n = 0; n < nsteps; ++n) rk3_step(tb, *t, ti, G.data(), G1.data(), G2.data(), L.data());
   for (int64_t a = 0; a < N; ++a) { F[a] = G[a].v; dF[a] = G[a].d; }
   return 0;

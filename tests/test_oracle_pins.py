@@ -416,3 +416,12 @@ def test_tangent_linear_model_matches_central_differences():
     out, dout = O.fields_tangent(tube, F0, dF)
     fd = (O.fields(tube, F0 + h * dF) - O.fields(tube, F0 - h * dF)) / (2 * h)
     assert np.abs(dout - fd).max() < 1e-6 * np.abs(dout).max()
+
+
+def test_tangent_is_finite_in_the_collisionless_limit():
+    tube = O.Tube(nx=32, q_xi=6, q_p=3, tau=math.inf)
+    F0 = O.run(tube, SOD_L, SOD_R, 4)
+    dF = np.random.default_rng(0).standard_normal(F0.shape)
+    _, jv = O.step_tangent(tube, F0, dF, 0.0, 2)
+    _, jt = O.step_tangent(tube, F0, np.zeros_like(F0), 1.0, 2)
+    assert np.all(np.isfinite(jv)) and np.all(jt == 0.0)
