@@ -176,6 +176,30 @@ rlb_status rlb_tube_info(const rlb_lattice* lat, int32_t tube, double* dt, doubl
  * xi[q_xi], w_xi[q_xi], p[q_p], w_p[q_p]. */
 rlb_status rlb_tables(const rlb_lattice* lat, int32_t tube, double* xi, double* w_xi, double* p, double* w_p);
 
+/*
+ * Discrete adjoint (reverse mode) of the time step, for gradients of a loss on
+ * the final fields with respect to tau and the initial states.  The lattice
+ * must have been created with RLB_WITH_ADJOINT.  All buffers are device
+ * memory in the state layout (see above); all calls are asynchronous unless
+ * noted.
+ *
+ * rlb_adjoint_step: lambda holds dL/df^{n+1} on entry and dL/df^n on return,
+ *   where f^{n+1} is the step (3 stages) applied to state_n = f^n.  The two
+ *   intermediate stages are recomputed from state_n.  dL_dtau[t] (device, one
+ *   double per tube) is incremented by the step's contribution to dL/dtau_t at
+ *   fixed time step.  state_n and lambda must not overlap.
+ * rlb_fields_adjoint: writes into tube's rows of lambda the gradient dL/df of a
+ *   loss on the fields of `state` (the rows of rlb_fields: N0, Nz, T00, T0z,
+ *   Tzz, e, n, v, T, |N|), given dL_dfields [10][ld] (device, FP64).
+ * rlb_initial_state_adjoint: given lambda0 = dL/df(t = 0), returns on the host
+ *   dL/d(P, n, u) of the left and right states of eq. condinit; synchronizes.
+ */
+rlb_status rlb_adjoint_step(rlb_lattice* lat, const void* state_n, void* lambda, double* dL_dtau);
+rlb_status rlb_fields_adjoint(rlb_lattice* lat, int32_t tube, const void* state, const double* dL_dfields, int64_t ld,
+                              void* lambda);
+rlb_status rlb_initial_state_adjoint(rlb_lattice* lat, int32_t tube, const void* lambda0, double grad_left[3],
+                                     double grad_right[3]);
+
 /* Plain device copy kernel (bandwidth calibration); asynchronous. */
 rlb_status rlb_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
 

@@ -1,0 +1,356 @@
+// Discrete adjoint of the SSP-RK3 lattice Boltzmann step (hand-written
+// reverse mode of the forward kernels in rlb_kernels.hip).
+//
+// For a stage input g the right-hand side is L(g) = A(g) + R(g) with
+//   A_s(x) = -(xi_j/dz) (H_s(x+1/2) - H_s(x-1/2))          (WENO5 advection)
+//   R_s(x) = -rho_s(x) (g_s(x) - e_s(x)),  rho = (gamma - xi u)/tau
+// where gamma, u, n, T come from the Landau matching of the moments m(x) of g
+// and e_s(x) is the truncated equilibrium.  Its transpose applied to K is
+//   (dL/dg)^T K = A^T K - rho K + B_s . mu(x),
+// with B_s the moment basis of point s and mu(x) = dR/dm^T K, obtained from a
+// reduction over the points of the cell followed by the adjoints of the
+// equilibrium projection and of the Landau matching.  Three kernels per stage:
+//   adj_reduce   one lane per cell: mu(x), the rate constants and d/dtau,
+//   adj_faces    one lane per (point, face): WENO5 gradient times the face
+//                adjoint phi = -(xi/dz)(K_left - K_right),
+//   adj_combine  one lane per (point, cell): gathers the face contributions
+//                (contributions to ghost cells fold into the edge cell, the
+//                transpose of the zero-gradient ghost copy) and forms the RK
+//                adjoint combination.
+#include <hip/hip_runtime.h>
+
+#include "rlb_device.h"
+#include "rlb_internal.h"
+
+namespace rlb {
+namespace {
+
+using namespace dev;
+
+template <typename Real, int QPT, int NVT>
+__global__ __launch_bounds__(256) void adj_reduce_kernel(AdjArgs<Real> a) {
+  const TubeDev& tb = a.tubes[a.tube];
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= tb.nx) return;
+  const int64_t ldx = tb.ldx;
+  const int qx = tb.qx, qp = tb.qp;
+  const cptr<Real> jtab = as_const(a.jtab) + int64_t(tb.jrow) * kJStride;
+  const cptr<double> itab = as_const(a.itab) + int64_t(tb.irow) * kIStride;
+  double m[5];
+  for (int c = 0; c < 5; ++c) m[c] = a.rec_g[tb.rec_off + c * ldx + y];
+  const Macro M = landau(m);
+  Real D[QPT][NVT + 1];
+  feq_coefficients<Real, QPT, NVT>(Real(M.n), Real(M.T), Real(M.gamma), Real(M.u), Real(tb.T0), qp, tb.np, tb.nv,
+                                   itab, as_const(a.aux), a.aux_pairs, D);
+  const double tau_inv = tb.tau_inv;
+  const Real g0 = Real(M.gamma * tau_inv), g1 = Real(M.u * tau_inv);
+  const Real* g = a.g + tb.f_off;
+  const Real* K = a.K + tb.f_off;
+  double Gb = 0.0, Ub = 0.0, taup = 0.0;
+  double Db[QPT][NVT + 1];
+#pragma unroll
+  for (int i = 0; i < QPT; ++i)
+#pragma unroll
+    for (int k = 0; k <= NVT; ++k) Db[i][k] = 0.0;
+#pragma unroll
+  for (int i = 0; i < QPT; ++i) {
+    if (i < qp) {
+      for (int j = 0; j < qx; ++j) {
+        const cptr<Real> J = jtab + j * kJStride;
+        const Real xi = J[0];
+        const int64_t row = int64_t(i * qx + j) * ldx;
+        const double Kv = double(K[row + y]);
+        Real e = Real(0);
+#pragma unroll
+        for (int k = 0; k <= NVT; ++k) e += D[i][k] * J[4 + k];
+        const double diff = double(g[row + y]) - double(e);
+        const double rho = double(g0 - xi * g1);
+        Gb -= Kv * diff * tau_inv;
+        Ub += Kv * double(xi) * diff * tau_inv;
+        const double kr = Kv * rho;
+#pragma unroll
+        for (int k = 0; k <= NVT; ++k) Db[i][k] += kr * double(J[4 + k]);
+        taup += kr * tau_inv * diff;
+      }
+    }
+  }
+  double nb = 0.0, Tb = 0.0, gb = Gb, ub = Ub;
+  feq_coefficients_adjoint<QPT, NVT>(M.n, M.T, M.gamma, M.u, tb.T0, qp, tb.np, tb.nv, itab, as_const(a.aux_d),
+                                     a.aux_pairs, Db, nb, Tb, gb, ub);
+  double mu[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  landau_adjoint(m, M, 0.0, 0.0, gb, ub, nb, Tb, mu);
+  double* cb = a.cellbuf + 7 * tb.cell_off;
+  for (int c = 0; c < 5; ++c) cb[c * ldx + y] = mu[c];
+  cb[5 * ldx + y] = double(g0);
+  cb[6 * ldx + y] = double(g1);
+  double* ta = a.tau_acc + tb.cell_off;
+  ta[y] = (a.tau_init ? 0.0 : ta[y]) + a.cJ * taup;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void adj_faces_kernel(AdjArgs<Real> a) {
+  const TubeDev& tb = a.tubes[a.tube];
+  const int nx = tb.nx;
+  const int fx = blockIdx.x * blockDim.x + threadIdx.x;  // face fx sits between cells fx-1 and fx
+  if (fx > nx) return;
+  const int s = blockIdx.y;
+  const int j = s % tb.qx;
+  const Real xi = a.jtab[int64_t(tb.jrow + j) * kJStride];
+  const Real* g = a.g + tb.f_off + int64_t(s) * tb.ldx;
+  const Real* K = a.K + tb.f_off + int64_t(s) * tb.ldx;
+  const int x = fx - 1;
+  auto G = [&](int p) { return g[p < 0 ? 0 : (p >= nx ? nx - 1 : p)]; };
+  Real gr[5];
+  const Real eps = Real(tb.weno_eps);
+  if (xi >= Real(0)) weno5_grad(G(x - 2), G(x - 1), G(x), G(x + 1), G(x + 2), eps, gr);
+  else weno5_grad(G(x + 3), G(x + 2), G(x + 1), G(x), G(x - 1), eps, gr);
+  const Real kl = (x >= 0) ? K[x] : Real(0);
+  const Real kr = (x + 1 < nx) ? K[x + 1] : Real(0);
+  const Real phi = -xi * Real(tb.dz_inv) * (kl - kr);
+  Real* out = a.G + tb.face_off + int64_t(s) * tb.ldf + fx;
+#pragma unroll
+  for (int m = 0; m < 5; ++m) out[m * a.G_slot] = phi * gr[m];
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void adj_combine_kernel(AdjArgs<Real> a) {
+  const TubeDev& tb = a.tubes[a.tube];
+  const int nx = tb.nx;
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= nx) return;
+  const int s = blockIdx.y;
+  const int i = s / tb.qx, j = s % tb.qx;
+  const Real* J = a.jtab + int64_t(tb.jrow + j) * kJStride;
+  const double* I = a.itab + int64_t(tb.irow + i) * kIStride;
+  const Real xi = J[0];
+  const bool pos = xi >= Real(0);
+  const Real* Gp = a.G + tb.face_off + int64_t(s) * tb.ldf;
+  // sum of the face contributions aimed at (unclamped) position p
+  auto at = [&](int p) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const int fx = pos ? p + 3 - m : p - 2 + m;
+      if (fx >= 0 && fx <= nx) acc += double(Gp[m * a.G_slot + fx]);
+    }
+    return acc;
+  };
+  double adv = at(y);
+  if (y == 0) adv += at(-1) + at(-2) + at(-3);
+  if (y == nx - 1) adv += at(nx) + at(nx + 1) + at(nx + 2);
+  const int64_t ldx = tb.ldx;
+  const double* cb = a.cellbuf + 7 * tb.cell_off;
+  const double mu0 = cb[y], mu1 = cb[ldx + y], mu2 = cb[2 * ldx + y], mu3 = cb[3 * ldx + y], mu4 = cb[4 * ldx + y];
+  const double rho = double(Real(cb[5 * ldx + y]) - xi * Real(cb[6 * ldx + y]));
+  const double Bmu = double(J[1]) * (I[2] * mu0 + I[3] * mu2) + double(J[2]) * (I[2] * mu1 + I[3] * mu3) +
+                     double(J[3]) * I[3] * mu4;
+  const int64_t idx = tb.f_off + int64_t(s) * ldx + y;
+  const double Kv = double(a.K[idx]);
+  double out = a.cK * Kv + a.cJ * (adv - rho * Kv + Bmu);
+  double accv = 0.0;
+  if (a.add_acc || (a.cA != 0.0 && !a.acc_init)) accv = double(a.acc_in[idx]);
+  if (a.add_acc) out += accv;
+  if (a.cA != 0.0) a.acc_out[idx] = Real((a.acc_init ? 0.0 : accv) + a.cA * Kv);
+  a.out[idx] = Real(out);
+}
+
+// dL/dtau[tube] += sum_x tau_acc[x] (fixed-order tree reduction).
+__global__ __launch_bounds__(256) void tau_reduce_kernel(const TubeDev* tubes, int tube, const double* tau_acc,
+                                                         double* dL_dtau) {
+  __shared__ double red[256];
+  const TubeDev& tb = tubes[tube];
+  double s = 0.0;
+  for (int x = threadIdx.x; x < tb.nx; x += blockDim.x) s += tau_acc[tb.cell_off + x];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dL_dtau[tube] += red[0];
+}
+
+// Adjoint of the diagnostic fields (N0, Nz, T00, T0z, Tzz, e, n, v, T, |N|)
+// of a state: lambda_s(x) = B_s . dL/dm(x).
+template <typename Real>
+__global__ __launch_bounds__(256) void fields_adjoint_kernel(const TubeDev* tubes, int tube, const Real* jtab_all,
+                                                             const double* itab_all, const double* rec,
+                                                             const double* dfields, int64_t ld, Real* lambda) {
+  const TubeDev& tb = tubes[tube];
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  if (y >= tb.nx) return;
+  const int64_t ldx = tb.ldx;
+  double m[5], mb[5];
+  for (int c = 0; c < 5; ++c) {
+    m[c] = rec[tb.rec_off + c * ldx + y];
+    mb[c] = dfields[c * ld + y];
+  }
+  const Macro M = landau(m);
+  landau_adjoint(m, M, dfields[5 * ld + y], dfields[7 * ld + y], 0.0, 0.0, dfields[6 * ld + y], dfields[8 * ld + y],
+                 mb);
+  const double nabs = sqrt((m[0] - m[1]) * (m[0] + m[1]));
+  const double nab = dfields[9 * ld + y];
+  mb[0] += nab * m[0] / nabs;
+  mb[1] -= nab * m[1] / nabs;
+  const Real* jtab = jtab_all + int64_t(tb.jrow) * kJStride;
+  const double* itab = itab_all + int64_t(tb.irow) * kIStride;
+  Real* lam = lambda + tb.f_off;
+  for (int i = 0; i < tb.qp; ++i) {
+    const double* I = itab + i * kIStride;
+    const double c1 = I[2] * mb[0] + I[3] * mb[2], c2 = I[2] * mb[1] + I[3] * mb[3], c3 = I[3] * mb[4];
+    for (int j = 0; j < tb.qx; ++j) {
+      const Real* J = jtab + j * kJStride;
+      lam[int64_t(i * tb.qx + j) * ldx + y] = Real(double(J[1]) * c1 + double(J[2]) * c2 + double(J[3]) * c3);
+    }
+  }
+}
+
+// Initial-state adjoint, pass 1: per block and side, sum over cells of
+// Db[i][k] = sum_j lambda0_s(x) P_k(xi_j)  (the adjoint of the coefficients
+// D[i][k] of the side's equilibrium).
+template <typename Real, int QPT, int NVT>
+__global__ __launch_bounds__(256) void init_adjoint_partial_kernel(const TubeDev* tubes, int tube, const Real* jtab_all,
+                                                                   const Real* lambda0, double* partials) {
+  __shared__ double red[2][256];
+  const TubeDev& tb = tubes[tube];
+  const int y = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = y < tb.nx;
+  const int side = valid ? ((tb.z_min + (y + 0.5) * tb.dz) < 0.0 ? 0 : 1) : 0;
+  const Real* jtab = jtab_all + int64_t(tb.jrow) * kJStride;
+  const Real* lam = lambda0 + tb.f_off;
+  constexpr int NC = QPT * (NVT + 1);
+  for (int c = 0; c < NC; ++c) {
+    const int i = c / (NVT + 1), k = c % (NVT + 1);
+    double v = 0.0;
+    if (valid && i < tb.qp && k <= tb.nv)
+      for (int j = 0; j < tb.qx; ++j)
+        v += double(lam[int64_t(i * tb.qx + j) * tb.ldx + y]) * double(jtab[j * kJStride + 4 + k]);
+    red[0][threadIdx.x] = side == 0 ? v : 0.0;
+    red[1][threadIdx.x] = side == 1 ? v : 0.0;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (threadIdx.x < w) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + w];
+        red[1][threadIdx.x] += red[1][threadIdx.x + w];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      partials[(int64_t(blockIdx.x) * 2 + 0) * NC + c] = red[0][0];
+      partials[(int64_t(blockIdx.x) * 2 + 1) * NC + c] = red[1][0];
+    }
+    __syncthreads();
+  }
+}
+
+// Pass 2: one lane per side sums the block partials in order and applies the
+// adjoint of the projection and of (P, n, u) -> (n, T = P/n, gamma, u).
+template <int QPT, int NVT>
+__global__ void init_adjoint_final_kernel(const TubeDev* tubes, int tube, const double* itab_all,
+                                          const double* aux_d, int aux_pairs, const double* sides,
+                                          const double* partials, int nblocks, double* grad_out) {
+  const int side = threadIdx.x;
+  if (side >= 2) return;
+  const TubeDev& tb = tubes[tube];
+  constexpr int NC = QPT * (NVT + 1);
+  double Db[QPT][NVT + 1];
+  for (int c = 0; c < NC; ++c) {
+    double v = 0.0;
+    for (int b = 0; b < nblocks; ++b) v += partials[(int64_t(b) * 2 + side) * NC + c];
+    Db[c / (NVT + 1)][c % (NVT + 1)] = v;
+  }
+  const double* st = sides + 6 * tube + 3 * side;
+  const double P = st[0], n = st[1], u = st[2];
+  const double T = P / n, gamma = sqrt(1.0 + u * u);
+  double nb = 0.0, Tb = 0.0, gb = 0.0, ub = 0.0;
+  feq_coefficients_adjoint<QPT, NVT>(n, T, gamma, u, tb.T0, tb.qp, tb.np, tb.nv,
+                                     as_const(itab_all) + int64_t(tb.irow) * kIStride, as_const(aux_d), aux_pairs,
+                                     Db, nb, Tb, gb, ub);
+  grad_out[3 * side + 0] = Tb / n;                  // dL/dP
+  grad_out[3 * side + 1] = nb - Tb * P / (n * n);   // dL/dn
+  grad_out[3 * side + 2] = ub + gb * u / gamma;     // dL/du
+}
+
+template <typename Real, int QPT, int NVT>
+hipError_t adjoint_stage_t(int nx, int Q, const AdjArgs<Real>& a, hipStream_t s) {
+  hipLaunchKernelGGL((adj_reduce_kernel<Real, QPT, NVT>), dim3((nx + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(adj_faces_kernel<Real>, dim3((nx + 1 + 255) / 256, Q), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(adj_combine_kernel<Real>, dim3((nx + 255) / 256, Q), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t adjoint_stage_real(int qpt, int nvt, int nx, int Q, const void* args, hipStream_t s) {
+  const AdjArgs<Real>& a = *static_cast<const AdjArgs<Real>*>(args);
+  if (qpt == 3 && nvt == 5) return adjoint_stage_t<Real, 3, 5>(nx, Q, a, s);
+  if (qpt == 4 && nvt == 5) return adjoint_stage_t<Real, 4, 5>(nx, Q, a, s);
+  if (qpt == 8 && nvt == 7) return adjoint_stage_t<Real, 8, 7>(nx, Q, a, s);
+  return hipErrorInvalidValue;
+}
+
+template <typename Real, int QPT, int NVT>
+hipError_t initial_adjoint_t(const TubeDev* tubes, int tube, int nx, const void* jtab, const double* itab,
+                             const double* aux_d, int aux_pairs, const double* sides, const void* lambda0,
+                             double* partials, double* grad_out, hipStream_t s) {
+  const int nblocks = (nx + 255) / 256;
+  hipLaunchKernelGGL((init_adjoint_partial_kernel<Real, QPT, NVT>), dim3(nblocks), dim3(256), 0, s, tubes, tube,
+                     static_cast<const Real*>(jtab), static_cast<const Real*>(lambda0), partials);
+  hipLaunchKernelGGL((init_adjoint_final_kernel<QPT, NVT>), dim3(1), dim3(64), 0, s, tubes, tube, itab, aux_d,
+                     aux_pairs, sides, partials, nblocks, grad_out);
+  return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t initial_adjoint_real(int qpt, int nvt, const TubeDev* tubes, int tube, int nx, const void* jtab,
+                                const double* itab, const double* aux_d, int aux_pairs, const double* sides,
+                                const void* lambda0, double* partials, double* grad_out, hipStream_t s) {
+  if (qpt == 3 && nvt == 5)
+    return initial_adjoint_t<Real, 3, 5>(tubes, tube, nx, jtab, itab, aux_d, aux_pairs, sides, lambda0, partials,
+                                         grad_out, s);
+  if (qpt == 4 && nvt == 5)
+    return initial_adjoint_t<Real, 4, 5>(tubes, tube, nx, jtab, itab, aux_d, aux_pairs, sides, lambda0, partials,
+                                         grad_out, s);
+  if (qpt == 8 && nvt == 7)
+    return initial_adjoint_t<Real, 8, 7>(tubes, tube, nx, jtab, itab, aux_d, aux_pairs, sides, lambda0, partials,
+                                         grad_out, s);
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_stage(int prec_fp32, int qpt, int nvt, int nx, int Q, const void* args, hipStream_t stream) {
+  return prec_fp32 ? adjoint_stage_real<float>(qpt, nvt, nx, Q, args, stream)
+                   : adjoint_stage_real<double>(qpt, nvt, nx, Q, args, stream);
+}
+
+hipError_t launch_tau_reduce(const TubeDev* tubes, int tube, const double* tau_acc, double* dL_dtau,
+                             hipStream_t stream) {
+  hipLaunchKernelGGL(tau_reduce_kernel, dim3(1), dim3(256), 0, stream, tubes, tube, tau_acc, dL_dtau);
+  return hipGetLastError();
+}
+
+hipError_t launch_fields_adjoint(int prec_fp32, const TubeDev* tubes, int tube, int nx, const void* jtab,
+                                 const double* itab, const double* rec, const double* dfields, int64_t ld,
+                                 void* lambda, hipStream_t stream) {
+  const dim3 grid((nx + 255) / 256);
+  if (prec_fp32)
+    hipLaunchKernelGGL(fields_adjoint_kernel<float>, grid, dim3(256), 0, stream, tubes, tube,
+                       static_cast<const float*>(jtab), itab, rec, dfields, ld, static_cast<float*>(lambda));
+  else
+    hipLaunchKernelGGL(fields_adjoint_kernel<double>, grid, dim3(256), 0, stream, tubes, tube,
+                       static_cast<const double*>(jtab), itab, rec, dfields, ld, static_cast<double*>(lambda));
+  return hipGetLastError();
+}
+
+hipError_t launch_initial_adjoint(int prec_fp32, int qpt, int nvt, const TubeDev* tubes, int tube, int nx,
+                                  const void* jtab, const double* itab, const double* aux_d, int aux_pairs,
+                                  const double* sides, const void* lambda0, double* partials, int nblocks_max,
+                                  double* grad_out, hipStream_t stream) {
+  if ((nx + 255) / 256 > nblocks_max) return hipErrorInvalidValue;
+  return prec_fp32 ? initial_adjoint_real<float>(qpt, nvt, tubes, tube, nx, jtab, itab, aux_d, aux_pairs, sides,
+                                                 lambda0, partials, grad_out, stream)
+                   : initial_adjoint_real<double>(qpt, nvt, tubes, tube, nx, jtab, itab, aux_d, aux_pairs, sides,
+                                                  lambda0, partials, grad_out, stream);
+}
+
+}  // namespace rlb

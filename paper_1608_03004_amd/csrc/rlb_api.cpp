@@ -49,8 +49,13 @@ struct rlb_lattice {
   int64_t state_elems = 0, rec_elems = 0;
   int max_items = 0, max_ldx = 0;
   size_t off_F[3] = {0, 0, 0}, off_rec[3] = {0, 0, 0};
-  size_t off_tubes = 0, off_jtab = 0, off_itab = 0, off_aux = 0, off_items = 0, off_sides = 0, off_mask = 0,
-         off_flag = 0, off_fields = 0, off_totals = 0, total = 0;
+  size_t off_tubes = 0, off_jtab = 0, off_itab = 0, off_aux = 0, off_aux_d = 0, off_items = 0, off_sides = 0,
+         off_mask = 0, off_flag = 0, off_fields = 0, off_totals = 0, total = 0;
+  // adjoint workspace (RLB_WITH_ADJOINT)
+  int64_t cell_elems = 0, face_elems = 0;
+  int init_blocks_max = 0;
+  size_t off_aF[2] = {0, 0}, off_arec[3] = {0, 0, 0}, off_lam2 = 0, off_lam1 = 0, off_acc = 0, off_G = 0,
+         off_cellbuf = 0, off_tauacc = 0, off_ipart = 0, off_grad = 0;
 
   // binding
   char* ws = nullptr;
@@ -412,6 +417,11 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
     td.group = qpt * 16 + nvt;
     td.f_off = f_off;
     td.rec_off = rec_off;
+    td.cell_off = rec_off / 5;
+    td.ldf = (d.nx + 1 + 63) / 64 * 64;
+    td.face_off = L->face_elems;
+    L->face_elems += int64_t(d.q_xi) * d.q_p * td.ldf;
+    L->init_blocks_max = std::max(L->init_blocks_max, (d.nx + 255) / 256);
     f_off += int64_t(d.q_xi) * d.q_p * td.ldx;
     rec_off += 5 * int64_t(td.ldx);
     L->max_ldx = std::max(L->max_ldx, td.ldx);
@@ -419,6 +429,7 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
   }
   L->state_elems = f_off;
   L->rec_elems = rec_off;
+  L->cell_elems = rec_off / 5;
   L->jtab_f.assign(L->jtab_d.begin(), L->jtab_d.end());
 
   // auxiliary projection rule: symmetric pairs of a Gauss-Legendre rule
@@ -449,12 +460,25 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
   L->off_jtab = o; o = align256(o + L->jtab_d.size() * L->rsize);
   L->off_itab = o; o = align256(o + L->itab.size() * 8);
   L->off_aux = o; o = align256(o + L->aux_d.size() * L->rsize);
+  L->off_aux_d = o; o = align256(o + L->aux_d.size() * 8);
   L->off_items = o; o = align256(o + size_t(L->max_items) * sizeof(WorkItem));
   L->off_sides = o; o = align256(o + L->sides_h.size() * 8);
   L->off_mask = o; o = align256(o + L->mask_h.size() * 4);
   L->off_flag = o; o = align256(o + 16);
   L->off_fields = o; o = align256(o + 10 * size_t(L->max_ldx) * 8);
   L->off_totals = o; o = align256(o + 4 * 8);
+  if (flags & RLB_WITH_ADJOINT) {
+    for (int k = 0; k < 2; ++k) { L->off_aF[k] = o; o = align256(o + L->state_elems * L->rsize); }
+    for (int k = 0; k < 3; ++k) { L->off_arec[k] = o; o = align256(o + L->rec_elems * 8); }
+    L->off_lam2 = o; o = align256(o + L->state_elems * L->rsize);
+    L->off_lam1 = o; o = align256(o + L->state_elems * L->rsize);
+    L->off_acc = o; o = align256(o + L->state_elems * L->rsize);
+    L->off_G = o; o = align256(o + 5 * size_t(L->face_elems) * L->rsize);
+    L->off_cellbuf = o; o = align256(o + 7 * size_t(L->cell_elems) * 8);
+    L->off_tauacc = o; o = align256(o + size_t(L->cell_elems) * 8);
+    L->off_ipart = o; o = align256(o + size_t(L->init_blocks_max) * 2 * kMaxQp * (kMaxNv + 1) * 8);
+    L->off_grad = o; o = align256(o + 8 * 8);
+  }
   L->total = o;
 
   int dev = 0;
@@ -500,6 +524,7 @@ rlb_status rlb_bind(rlb_lattice* L, void* workspace, size_t bytes, void* hip_str
     if ((st = upload(L, L->off_aux, L->aux_d.data(), L->aux_d.size() * 8)) != RLB_OK) return st;
   }
   if ((st = upload(L, L->off_itab, L->itab.data(), L->itab.size() * 8)) != RLB_OK) return st;
+  if ((st = upload(L, L->off_aux_d, L->aux_d.data(), L->aux_d.size() * 8)) != RLB_OK) return st;
   if ((st = upload(L, L->off_items, L->items.data(), L->items.size() * sizeof(WorkItem))) != RLB_OK) return st;
   HIP_TRY(L, hipMemsetAsync(L->ws + L->off_flag, 0, 16, L->stream));
   HIP_TRY(L, hipStreamSynchronize(L->stream));
@@ -752,6 +777,197 @@ rlb_status rlb_tables(const rlb_lattice* L, int32_t tube, double* xi, double* w_
   if (w_xi) std::copy(L->wxi[tube].begin(), L->wxi[tube].end(), w_xi);
   if (p) std::copy(L->p[tube].begin(), L->p[tube].end(), p);
   if (w_p) std::copy(L->wp[tube].begin(), L->wp[tube].end(), w_p);
+  return RLB_OK;
+}
+
+
+}  // extern "C"
+
+namespace {
+
+// One forward stage over every tube with explicit buffers (adjoint recompute).
+rlb_status run_stage(rlb_lattice* L, int stage, const void* fin, const void* fn, void* fout, const double* rec_in,
+                     double* rec_out) {
+  const bool fp32 = L->prec == RLB_FP32;
+  for (const Group& g : L->groups) {
+    const LaunchShape ls = shape(L, g);
+    hipError_t e;
+    if (fp32) {
+      StageArgs<float> a;
+      a.tubes = L->dev<TubeDev>(L->off_tubes);
+      a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
+      a.nitems = g.item_end - g.item_begin;
+      a.stage = stage;
+      a.aux_pairs = L->aux_pairs;
+      a.jtab = L->dev<float>(L->off_jtab);
+      a.itab = L->dev<double>(L->off_itab);
+      a.aux = L->dev<float>(L->off_aux);
+      a.fin = static_cast<const float*>(fin);
+      a.fn = static_cast<const float*>(fn);
+      a.fout = static_cast<float*>(fout);
+      a.rec_in = rec_in;
+      a.rec_out = rec_out;
+      a.flag = L->dev<unsigned>(L->off_flag);
+      e = launch_stage(1, g.qpt, g.nvt, ls, &a, L->stream);
+    } else {
+      StageArgs<double> a;
+      a.tubes = L->dev<TubeDev>(L->off_tubes);
+      a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
+      a.nitems = g.item_end - g.item_begin;
+      a.stage = stage;
+      a.aux_pairs = L->aux_pairs;
+      a.jtab = L->dev<double>(L->off_jtab);
+      a.itab = L->dev<double>(L->off_itab);
+      a.aux = L->dev<double>(L->off_aux);
+      a.fin = static_cast<const double*>(fin);
+      a.fn = static_cast<const double*>(fn);
+      a.fout = static_cast<double*>(fout);
+      a.rec_in = rec_in;
+      a.rec_out = rec_out;
+      a.flag = L->dev<unsigned>(L->off_flag);
+      e = launch_stage(0, g.qpt, g.nvt, ls, &a, L->stream);
+    }
+    if (e != hipSuccess) return hip_fail(L, e, "stage kernel launch");
+  }
+  return RLB_OK;
+}
+
+rlb_status moments_of(rlb_lattice* L, const void* state, double* rec) {
+  hipError_t e = launch_moments(L->prec == RLB_FP32 ? 1 : 0, L->dev<TubeDev>(L->off_tubes),
+                                L->dev<WorkItem>(L->off_items), static_cast<int>(L->items.size()), L->sched.tile,
+                                L->ws + L->off_jtab, L->dev<double>(L->off_itab), state, rec, L->stream);
+  if (e != hipSuccess) return hip_fail(L, e, "moments kernel launch");
+  return RLB_OK;
+}
+
+template <typename Real>
+rlb_status adjoint_stage(rlb_lattice* L, int tube, int qpt, int nvt, const void* g, const double* rec_g, const void* K,
+                         void* out, const void* acc_in, void* acc_out, double cK, double cJ, double cA, int add_acc,
+                         int acc_init, int tau_init) {
+  AdjArgs<Real> a;
+  a.tubes = L->dev<TubeDev>(L->off_tubes);
+  a.tube = tube;
+  a.aux_pairs = L->aux_pairs;
+  a.jtab = L->dev<Real>(L->off_jtab);
+  a.itab = L->dev<double>(L->off_itab);
+  a.aux = L->dev<Real>(L->off_aux);
+  a.aux_d = L->dev<double>(L->off_aux_d);
+  a.g = static_cast<const Real*>(g);
+  a.rec_g = rec_g;
+  a.K = static_cast<const Real*>(K);
+  a.acc_in = static_cast<const Real*>(acc_in);
+  a.out = static_cast<Real*>(out);
+  a.acc_out = static_cast<Real*>(acc_out);
+  a.cellbuf = L->dev<double>(L->off_cellbuf);
+  a.tau_acc = L->dev<double>(L->off_tauacc);
+  a.G = L->dev<Real>(L->off_G);
+  a.G_slot = L->face_elems;
+  a.cK = cK;
+  a.cJ = cJ;
+  a.cA = cA;
+  a.add_acc = add_acc;
+  a.acc_init = acc_init;
+  a.tau_init = tau_init;
+  const TubeDev& td = L->tubes[tube];
+  hipError_t e = launch_adjoint_stage(L->prec == RLB_FP32 ? 1 : 0, qpt, nvt, td.nx, td.qx * td.qp, &a, L->stream);
+  if (e != hipSuccess) return hip_fail(L, e, "adjoint kernel launch");
+  return RLB_OK;
+}
+
+rlb_status need_adjoint(rlb_lattice* L) {
+  rlb_status st = need_ready(L, false);
+  if (st != RLB_OK) return st;
+  if (!(L->flags & RLB_WITH_ADJOINT)) return fail(L, RLB_ERR_STATE, "lattice was created without RLB_WITH_ADJOINT");
+  return RLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rlb_status rlb_adjoint_step(rlb_lattice* L, const void* state_n, void* lambda, double* dL_dtau) {
+  rlb_status st = need_adjoint(L);
+  if (st != RLB_OK) return st;
+  if (!state_n || !lambda || !dL_dtau) return fail(L, RLB_ERR_INVALID_ARG, "state_n, lambda and dL_dtau are required");
+  if (state_n == lambda) return fail(L, RLB_ERR_INVALID_ARG, "state_n and lambda must not alias");
+  void* F1 = L->ws + L->off_aF[0];
+  void* F2 = L->ws + L->off_aF[1];
+  double* r0 = L->dev<double>(L->off_arec[0]);
+  double* r1 = L->dev<double>(L->off_arec[1]);
+  double* r2 = L->dev<double>(L->off_arec[2]);
+  // recompute the two intermediate stages of the step from f^n
+  if ((st = moments_of(L, state_n, r0)) != RLB_OK) return st;
+  if ((st = run_stage(L, 1, state_n, state_n, F1, r0, r1)) != RLB_OK) return st;
+  if ((st = run_stage(L, 2, F1, state_n, F2, r1, r2)) != RLB_OK) return st;
+  void* lam2 = L->ws + L->off_lam2;
+  void* lam1 = L->ws + L->off_lam1;
+  void* acc = L->ws + L->off_acc;
+  const bool fp32 = L->prec == RLB_FP32;
+  for (const Group& g : L->groups) {
+    for (int it = g.item_begin; it < g.item_end; ++it) {
+      if (L->items[it].x0 != 0) continue;  // one pass per tube
+      const int t = L->items[it].tube;
+      const double dt = L->tubes[t].dt;
+      auto stage = [&](const void* gs, const double* rec, const void* K, void* out, const void* ain, void* aout,
+                       double cK, double cJ, double cA, int add_acc, int acc_init, int tau_init) {
+        return fp32 ? adjoint_stage<float>(L, t, g.qpt, g.nvt, gs, rec, K, out, ain, aout, cK, cJ, cA, add_acc,
+                                           acc_init, tau_init)
+                    : adjoint_stage<double>(L, t, g.qpt, g.nvt, gs, rec, K, out, ain, aout, cK, cJ, cA, add_acc,
+                                            acc_init, tau_init);
+      };
+      // f^{n+1} = 1/3 f^n + 2/3 (f2 + dt L(f2))
+      if ((st = stage(F2, r2, lambda, lam2, nullptr, acc, 2.0 / 3.0, 2.0 / 3.0 * dt, 1.0 / 3.0, 0, 1, 1)) != RLB_OK)
+        return st;
+      // f2 = 3/4 f^n + 1/4 (f1 + dt L(f1))
+      if ((st = stage(F1, r1, lam2, lam1, acc, acc, 0.25, 0.25 * dt, 0.75, 0, 0, 0)) != RLB_OK) return st;
+      // f1 = f^n + dt L(f^n)
+      if ((st = stage(state_n, r0, lam1, lambda, acc, nullptr, 1.0, dt, 0.0, 1, 0, 0)) != RLB_OK) return st;
+      hipError_t e = launch_tau_reduce(L->dev<TubeDev>(L->off_tubes), t, L->dev<double>(L->off_tauacc), dL_dtau,
+                                       L->stream);
+      if (e != hipSuccess) return hip_fail(L, e, "tau reduction launch");
+    }
+  }
+  return RLB_OK;
+}
+
+rlb_status rlb_fields_adjoint(rlb_lattice* L, int32_t tube, const void* state, const double* dL_dfields, int64_t ld,
+                              void* lambda) {
+  rlb_status st = need_adjoint(L);
+  if (st != RLB_OK) return st;
+  if (!check_tube(L, tube)) return fail(L, RLB_ERR_INVALID_ARG, "tube index out of range");
+  if (!state || !dL_dfields || !lambda || ld < L->tubes[tube].nx)
+    return fail(L, RLB_ERR_INVALID_ARG, "need state, dL_dfields, lambda and ld >= nx");
+  double* r0 = L->dev<double>(L->off_arec[0]);
+  if ((st = moments_of(L, state, r0)) != RLB_OK) return st;
+  hipError_t e = launch_fields_adjoint(L->prec == RLB_FP32 ? 1 : 0, L->dev<TubeDev>(L->off_tubes), tube,
+                                       L->tubes[tube].nx, L->ws + L->off_jtab, L->dev<double>(L->off_itab), r0,
+                                       dL_dfields, ld, lambda, L->stream);
+  if (e != hipSuccess) return hip_fail(L, e, "fields adjoint launch");
+  return RLB_OK;
+}
+
+rlb_status rlb_initial_state_adjoint(rlb_lattice* L, int32_t tube, const void* lambda0, double grad_left[3],
+                                     double grad_right[3]) {
+  rlb_status st = need_adjoint(L);
+  if (st != RLB_OK) return st;
+  if (!check_tube(L, tube) || !lambda0 || !grad_left || !grad_right)
+    return fail(L, RLB_ERR_INVALID_ARG, "bad tube or NULL argument");
+  if (!L->initialised) return fail(L, RLB_ERR_STATE, "no initial state has been set");
+  int qpt, nvt;
+  kernel_group(L->desc[tube].q_p, L->desc[tube].n_v, &qpt, &nvt);
+  double* grad = L->dev<double>(L->off_grad);
+  hipError_t e = launch_initial_adjoint(L->prec == RLB_FP32 ? 1 : 0, qpt, nvt, L->dev<TubeDev>(L->off_tubes), tube,
+                                        L->tubes[tube].nx, L->ws + L->off_jtab, L->dev<double>(L->off_itab),
+                                        L->dev<double>(L->off_aux_d), L->aux_pairs, L->dev<double>(L->off_sides),
+                                        lambda0, L->dev<double>(L->off_ipart), L->init_blocks_max, grad, L->stream);
+  if (e != hipSuccess) return hip_fail(L, e, "initial-state adjoint launch");
+  double h[6];
+  HIP_TRY(L, hipMemcpyAsync(h, grad, sizeof h, hipMemcpyDeviceToHost, L->stream));
+  HIP_TRY(L, hipStreamSynchronize(L->stream));
+  for (int k = 0; k < 3; ++k) {
+    grad_left[k] = h[k];
+    grad_right[k] = h[3 + k];
+  }
   return RLB_OK;
 }
 

@@ -1,0 +1,287 @@
+// Device-side arithmetic shared by the forward and adjoint kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "rlb_internal.h"
+
+namespace rlb {
+namespace dev {
+
+// Read-only kernel inputs (tube descriptors, work lists, quadrature tables) are
+// read through the constant address space so that wave-uniform reads become
+// scalar loads into SGPRs instead of 64-lane vector loads.
+template <typename T>
+using cptr = __attribute__((address_space(4))) const T*;
+template <typename T>
+__device__ inline cptr<T> as_const(const T* p) {
+  return (cptr<T>)(p);
+}
+
+// n/d with one hardware reciprocal: FP32 takes one correction step (< 2 ulp);
+// FP64 refines the reciprocal twice by Newton's method and corrects the
+// quotient once, which is close to correctly rounded.
+__device__ inline float fast_div(float n, float d) {
+  const float r = __builtin_amdgcn_rcpf(d);
+  const float q = n * r;
+  return fmaf(r, fmaf(-d, q, n), q);
+}
+__device__ inline double fast_div(double n, double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  const double q = n * r;
+  return fma(r, fma(-d, q, n), q);
+}
+
+// ---------------------------------------------------------------------------
+// Small arithmetic helpers
+// ---------------------------------------------------------------------------
+template <typename Real>
+struct Acc;  // moment accumulator over the polar nodes of one radial node
+
+template <>
+struct Acc<double> {
+  double s = 0.0;
+  __device__ void add(double x) { s += x; }
+  __device__ double value() const { return s; }
+};
+
+// Kahan-compensated FP32 sum.
+template <>
+struct Acc<float> {
+  float s = 0.0f, c = 0.0f;
+  __device__ void add(float x) {
+    const float y = x - c;
+    const float t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+  __device__ double value() const { return double(s) - double(c); }
+};
+
+struct Macro {
+  double e, v, gamma, u, n, T;
+  bool ok;
+};
+
+// Landau matching T^mu_nu u^nu = -e u^mu for the 1D moments
+// m = (N0, Nz, T00, T0z, Tzz) (section Relativistic LB equation).  The 2x2
+// eigenproblem in the t-z block gives e = (T00 - Tzz + D)/2 and
+// v = 2 T0z / (T00 + Tzz + D) with D^2 = (T00+Tzz)^2 - 4 T0z^2; the density is
+// n = -u_mu N^mu and the temperature T = e/(3n) (massless gas, e = 3P = 3nT).
+__device__ inline Macro landau(const double m[5]) {
+  Macro M;
+  const double a = m[2] + m[4];
+  const double disc = (a - 2.0 * m[3]) * (a + 2.0 * m[3]);
+  const double D = sqrt(disc);
+  M.e = 0.5 * (m[2] - m[4] + D);
+  M.v = 2.0 * m[3] / (a + D);
+  M.gamma = 1.0 / sqrt((1.0 - M.v) * (1.0 + M.v));
+  M.u = M.gamma * M.v;
+  M.n = M.gamma * (m[0] - M.v * m[1]);
+  M.T = M.e / (3.0 * M.n);
+  M.ok = (disc >= 0.0) && (M.e > 0.0) && (M.n > 0.0) && (fabs(M.v) < 1.0) && isfinite(M.T);
+  return M;
+}
+
+// Coefficients of the truncated equilibrium at the radial nodes:
+//   F_eq(p_i, xi) = sum_{k<=n_v} D[i][k] P_k(xi),
+//   D[i][k] = (2k+1)/2 int_{-1}^{1} P_k(xi) G_i(xi) dxi,
+//   G_i(xi) = n/(4 T T0^2) y^2 sum_{l<=n_p} L_l(p_i) (1 - (T/T0) y)^l,
+//   y = 1/(gamma - xi u),
+// which is the orthogonal projection of eq. feqtrunc (the Laplace transform of
+// the Laguerre polynomials done in closed form, the xi integral by a symmetric
+// auxiliary Gauss-Legendre rule whose node pairs +-xi_a share one pass).
+template <typename Real, int QPT, int NVT>
+__device__ inline void feq_coefficients(Real n, Real T, Real gamma, Real u, Real T0, int qp, int np, int nv,
+                                        cptr<double> itab, cptr<Real> aux,
+                                        int aux_pairs, Real D[QPT][NVT + 1]) {
+#pragma unroll
+  for (int i = 0; i < QPT; ++i)
+#pragma unroll
+    for (int k = 0; k <= NVT; ++k) D[i][k] = Real(0);
+  const Real r = T / T0;
+  for (int a = 0; a < aux_pairs; ++a) {
+    cptr<Real> A = aux + a * kAuxStride;
+    const Real xa = A[0];
+    const Real yp = fast_div(Real(1), gamma - xa * u);
+    const Real ym = fast_div(Real(1), gamma + xa * u);
+    const Real qp_ = Real(1) - r * yp, qm = Real(1) - r * ym;
+    const Real yp2 = yp * yp, ym2 = ym * ym;
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+      if (i < qp) {
+        cptr<double> L = itab + i * kIStride + 4;
+        Real sp = Real(L[np]), sm = Real(L[np]);
+        for (int l = np - 1; l >= 0; --l) {
+          sp = sp * qp_ + Real(L[l]);
+          sm = sm * qm + Real(L[l]);
+        }
+        const Real gp = yp2 * sp, gm = ym2 * sm;
+        const Real ev = gp + gm, od = gp - gm;
+#pragma unroll
+        for (int k = 0; k <= NVT; ++k) D[i][k] += A[1 + k] * ((k & 1) ? od : ev);
+      }
+    }
+  }
+  const Real pref = n / (Real(4) * T * T0 * T0);
+#pragma unroll
+  for (int i = 0; i < QPT; ++i)
+#pragma unroll
+    for (int k = 0; k <= NVT; ++k) D[i][k] = (k <= nv) ? D[i][k] * pref : Real(0);
+}
+
+// Fifth-order WENO (Jiang-Shu) value at the face between v3 and v4 from the
+// upwind-ordered values v1..v5.  The three nonlinear weights
+// alpha_r = d_r/(eps+beta_r)^2 are normalised with a single division by
+// multiplying numerator and denominator by prod_r (eps+beta_r)^2.
+template <typename Real>
+__device__ inline Real weno5(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps) {
+  const Real q0 = (Real(2) * v1 - Real(7) * v2 + Real(11) * v3) * Real(1.0 / 6.0);
+  const Real q1 = (-v2 + Real(5) * v3 + Real(2) * v4) * Real(1.0 / 6.0);
+  const Real q2 = (Real(2) * v3 + Real(5) * v4 - v5) * Real(1.0 / 6.0);
+  const Real t0 = v1 - Real(2) * v2 + v3, s0 = v1 - Real(4) * v2 + Real(3) * v3;
+  const Real t1 = v2 - Real(2) * v3 + v4, s1 = v2 - v4;
+  const Real t2 = v3 - Real(2) * v4 + v5, s2 = Real(3) * v3 - Real(4) * v4 + v5;
+  const Real c13 = Real(13.0 / 12.0), c14 = Real(0.25);
+  const Real e0 = eps + c13 * t0 * t0 + c14 * s0 * s0;
+  const Real e1 = eps + c13 * t1 * t1 + c14 * s1 * s1;
+  const Real e2 = eps + c13 * t2 * t2 + c14 * s2 * s2;
+  const Real A = e0 * e0, B = e1 * e1, C = e2 * e2;
+  const Real a0 = Real(0.1) * (B * C), a1 = Real(0.6) * (A * C), a2 = Real(0.3) * (A * B);
+  return fast_div(a0 * q0 + a1 * q1 + a2 * q2, a0 + a1 + a2);
+}
+
+
+// ---------------------------------------------------------------------------
+// Reverse-mode derivatives (hand-written) of the per-cell maps above.
+// ---------------------------------------------------------------------------
+
+// Adjoint of the Landau matching: given the adjoints of (e, v, gamma, u, n, T)
+// at the moments m, accumulates the adjoint of m into mb.
+__device__ inline void landau_adjoint(const double m[5], const Macro& M, double eb, double vb, double gb, double ub,
+                                      double nb, double Tb, double mb[5]) {
+  const double a = m[2] + m[4], b = m[3];
+  const double D = sqrt((a - 2.0 * b) * (a + 2.0 * b));
+  // T = e/(3n)
+  eb += Tb / (3.0 * M.n);
+  nb -= Tb * M.T / M.n;
+  // n = gamma (N0 - v Nz)
+  gb += nb * (m[0] - M.v * m[1]);
+  mb[0] += nb * M.gamma;
+  mb[1] -= nb * M.gamma * M.v;
+  vb -= nb * M.gamma * m[1];
+  // u = gamma v
+  gb += ub * M.v;
+  vb += ub * M.gamma;
+  // gamma = (1 - v^2)^(-1/2)
+  vb += gb * M.gamma * M.gamma * M.gamma * M.v;
+  // v = 2b/(a + D)
+  const double iad = 1.0 / (a + D);
+  double bb = vb * 2.0 * iad;
+  double ab = -vb * M.v * iad;
+  double Db = -vb * M.v * iad;
+  // e = (T00 - Tzz + D)/2
+  mb[2] += 0.5 * eb;
+  mb[4] -= 0.5 * eb;
+  Db += 0.5 * eb;
+  // D = sqrt(a^2 - 4b^2)
+  ab += Db * a / D;
+  bb -= Db * 4.0 * b / D;
+  mb[2] += ab;
+  mb[4] += ab;
+  mb[3] += bb;
+}
+
+// Adjoint of feq_coefficients (evaluated in FP64 on the same auxiliary rule):
+// given Db[i][k] = dL/dD[i][k], accumulates dL/d(n, T, gamma, u).
+template <int QPT, int NVT>
+__device__ inline void feq_coefficients_adjoint(double n, double T, double gamma, double u, double T0, int qp, int np,
+                                                int nv, cptr<double> itab, cptr<double> aux, int aux_pairs,
+                                                const double Db[QPT][NVT + 1], double& nb, double& Tb, double& gb,
+                                                double& ub) {
+  const double pref = n / (4.0 * T * T0 * T0);
+  const double r = T / T0;
+  double prefb = 0.0, rb = 0.0;
+  for (int a = 0; a < aux_pairs; ++a) {
+    cptr<double> A = aux + a * kAuxStride;
+    const double xa = A[0];
+    const double yp = 1.0 / (gamma - xa * u), ym = 1.0 / (gamma + xa * u);
+    const double qp_ = 1.0 - r * yp, qm = 1.0 - r * ym;
+    const double yp2 = yp * yp, ym2 = ym * ym;
+    double ypb = 0.0, ymb = 0.0;
+#pragma unroll
+    for (int i = 0; i < QPT; ++i) {
+      if (i < qp) {
+        cptr<double> L = itab + i * kIStride + 4;
+        // P(q) = sum_l L_l q^l and P'(q) by Horner
+        double sp = L[np], dsp = 0.0, sm = L[np], dsm = 0.0;
+        for (int l = np - 1; l >= 0; --l) {
+          dsp = dsp * qp_ + sp;
+          sp = sp * qp_ + L[l];
+          dsm = dsm * qm + sm;
+          sm = sm * qm + L[l];
+        }
+        const double gp = yp2 * sp, gm = ym2 * sm;
+        double ev = 0.0, od = 0.0;
+#pragma unroll
+        for (int k = 0; k <= NVT; ++k) {
+          if (k <= nv) {
+            if (k & 1) od += Db[i][k] * A[1 + k];
+            else ev += Db[i][k] * A[1 + k];
+          }
+        }
+        prefb += ev * (gp + gm) + od * (gp - gm);
+        const double gpb = pref * (ev + od), gmb = pref * (ev - od);
+        ypb += gpb * 2.0 * yp * sp;
+        ymb += gmb * 2.0 * ym * sm;
+        const double qpb = gpb * yp2 * dsp, qmb = gmb * ym2 * dsm;
+        rb -= qpb * yp + qmb * ym;
+        ypb -= qpb * r;
+        ymb -= qmb * r;
+      }
+    }
+    gb -= ypb * yp2 + ymb * ym2;
+    ub += ypb * xa * yp2 - ymb * xa * ym2;
+  }
+  nb += prefb * pref / n;
+  Tb += -prefb * pref / T + rb / T0;
+}
+
+// Gradient of the WENO5 value with respect to its five upwind-ordered inputs.
+template <typename Real>
+__device__ inline void weno5_grad(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps, Real g[5]) {
+  const Real q0 = (Real(2) * v1 - Real(7) * v2 + Real(11) * v3) * Real(1.0 / 6.0);
+  const Real q1 = (-v2 + Real(5) * v3 + Real(2) * v4) * Real(1.0 / 6.0);
+  const Real q2 = (Real(2) * v3 + Real(5) * v4 - v5) * Real(1.0 / 6.0);
+  const Real t0 = v1 - Real(2) * v2 + v3, s0 = v1 - Real(4) * v2 + Real(3) * v3;
+  const Real t1 = v2 - Real(2) * v3 + v4, s1 = v2 - v4;
+  const Real t2 = v3 - Real(2) * v4 + v5, s2 = Real(3) * v3 - Real(4) * v4 + v5;
+  const Real c13 = Real(13.0 / 12.0), c14 = Real(0.25);
+  const Real e0 = eps + c13 * t0 * t0 + c14 * s0 * s0;
+  const Real e1 = eps + c13 * t1 * t1 + c14 * s1 * s1;
+  const Real e2 = eps + c13 * t2 * t2 + c14 * s2 * s2;
+  const Real a0 = Real(0.1) / (e0 * e0), a1 = Real(0.6) / (e1 * e1), a2 = Real(0.3) / (e2 * e2);
+  const Real sa = a0 + a1 + a2;
+  const Real w0 = a0 / sa, w1 = a1 / sa, w2 = a2 / sa;
+  const Real H = w0 * q0 + w1 * q1 + w2 * q2;
+  // d alpha_r = -2 alpha_r/(eps+beta_r) d beta_r ; dH/d alpha_r = (q_r - H)/sum(alpha)
+  const Real c0 = -Real(2) * w0 * (q0 - H) / e0;
+  const Real c1 = -Real(2) * w1 * (q1 - H) / e1;
+  const Real c2 = -Real(2) * w2 * (q2 - H) / e2;
+  // d beta_r / d v = (13/6) t_r dt_r + (1/2) s_r ds_r
+  const Real b0t = Real(13.0 / 6.0) * t0, b0s = Real(0.5) * s0;
+  const Real b1t = Real(13.0 / 6.0) * t1, b1s = Real(0.5) * s1;
+  const Real b2t = Real(13.0 / 6.0) * t2, b2s = Real(0.5) * s2;
+  const Real r6 = Real(1.0 / 6.0);
+  g[0] = w0 * Real(2) * r6 + c0 * (b0t + b0s);
+  g[1] = w0 * Real(-7) * r6 + w1 * Real(-1) * r6 + c0 * (Real(-2) * b0t - Real(4) * b0s) + c1 * (b1t + b1s);
+  g[2] = w0 * Real(11) * r6 + w1 * Real(5) * r6 + w2 * Real(2) * r6 + c0 * (b0t + Real(3) * b0s) +
+         c1 * (Real(-2) * b1t) + c2 * (b2t + Real(3) * b2s);
+  g[3] = w1 * Real(2) * r6 + w2 * Real(5) * r6 + c1 * (b1t - b1s) + c2 * (Real(-2) * b2t - Real(4) * b2s);
+  g[4] = w2 * Real(-1) * r6 + c2 * (b2t + b2s);
+}
+
+}  // namespace dev
+}  // namespace rlb

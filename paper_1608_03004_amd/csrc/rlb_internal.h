@@ -34,7 +34,37 @@ struct TubeDev {
   int32_t jrow, irow;  // first row of the tube in the polar / radial tables
   double z_min, dz, dz_inv, dt, tau_inv, T0, weno_eps;
   int32_t group;    // kernel instantiation group
-  int32_t pad;
+  int32_t ldf;      // row stride of the adjoint face buffer (>= nx + 1)
+  int64_t cell_off; // offset of the tube in per-cell arrays (sum of ldx of earlier tubes)
+  int64_t face_off; // element offset of the tube in one slot of the adjoint face buffer
+};
+
+// Arguments of the adjoint kernels of one stage of one tube.  For the stage
+// g -> out = a g_n + b (g + dt L(g)) the adjoint step forms, per point,
+//   out    = cK K + cJ (dL/dg)^T K (+ acc_in if add_acc)
+//   acc    = (acc_init ? 0 : acc) + cA K
+// where K is the adjoint of the stage output.
+template <typename Real>
+struct AdjArgs {
+  const TubeDev* tubes;
+  int32_t tube;
+  int32_t aux_pairs;
+  const Real* jtab;
+  const double* itab;
+  const Real* aux;
+  const double* aux_d;
+  const Real* g;
+  const double* rec_g;
+  const Real* K;
+  const Real* acc_in;
+  Real* out;
+  Real* acc_out;
+  double* cellbuf;  // per cell: mu[5], gamma/tau, u/tau  ([7][ldx] per tube)
+  double* tau_acc;  // per cell d/dtau partials ([ldx] per tube)
+  Real* G;          // face contributions, 5 slots of the state-like face layout
+  int64_t G_slot;   // elements per slot
+  double cK, cJ, cA;
+  int32_t add_acc, acc_init, tau_init;
 };
 
 // Work item of the stage kernels: a tile of cells of one tube.
@@ -92,5 +122,17 @@ hipError_t launch_fields(const TubeDev* tubes, int tube, int nx, const double* r
                          unsigned* flag, hipStream_t stream);
 hipError_t launch_totals(const TubeDev* tubes, int tube, const double* rec, double* out, hipStream_t stream);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+
+// Adjoint launchers (defined in rlb_adjoint.hip); one tube per call.
+hipError_t launch_adjoint_stage(int prec_fp32, int qpt, int nvt, int nx, int Q, const void* args, hipStream_t stream);
+hipError_t launch_tau_reduce(const TubeDev* tubes, int tube, const double* tau_acc, double* dL_dtau,
+                             hipStream_t stream);
+hipError_t launch_fields_adjoint(int prec_fp32, const TubeDev* tubes, int tube, int nx, const void* jtab,
+                                 const double* itab, const double* rec, const double* dfields, int64_t ld,
+                                 void* lambda, hipStream_t stream);
+hipError_t launch_initial_adjoint(int prec_fp32, int qpt, int nvt, const TubeDev* tubes, int tube, int nx,
+                                  const void* jtab, const double* itab, const double* aux_d, int aux_pairs,
+                                  const double* sides, const void* lambda0, double* partials, int nblocks_max,
+                                  double* grad_out, hipStream_t stream);
 
 }  // namespace rlb

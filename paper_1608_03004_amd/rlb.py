@@ -82,6 +82,9 @@ _SIGNATURES = {
     "rlb_tube_info": [_VP, ctypes.c_int32, _DP, _DP, ctypes.POINTER(ctypes.c_int32)],
     "rlb_tables": [_VP, ctypes.c_int32, _DP, _DP, _DP, _DP],
     "rlb_device_copy": [_VP, _VP, ctypes.c_size_t, _VP],
+    "rlb_adjoint_step": [_VP, _VP, _VP, _VP],
+    "rlb_fields_adjoint": [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_int64, _VP],
+    "rlb_initial_state_adjoint": [_VP, ctypes.c_int32, _VP, _DP, _DP],
 }
 _STRING_FUNCS = {"rlb_status_string": [ctypes.c_int], "rlb_last_error": [_VP]}
 
@@ -291,6 +294,35 @@ class Lattice:
         xi, wxi, p, wp = (np.zeros(t.q_xi), np.zeros(t.q_xi), np.zeros(t.q_p), np.zeros(t.q_p))
         self._check(self.lib.rlb_tables(self.h, tube, *(a.ctypes.data_as(_DP) for a in (xi, wxi, p, wp))))
         return xi, wxi, p, wp
+
+
+def _lattice_adjoint_methods():
+    def adjoint_step(self, state_n, lam, dL_dtau):
+        """lam: dL/df^{n+1} -> dL/df^n (in place); dL_dtau (device FP64, one per tube) is incremented."""
+        for t in (state_n, lam):
+            assert t.dtype == self.dtype and t.is_contiguous() and t.numel() >= self.state_elems
+        assert dL_dtau.dtype.is_floating_point and dL_dtau.element_size() == 8 and dL_dtau.numel() >= len(self.tubes)
+        self._check(self.lib.rlb_adjoint_step(self.h, _VP(state_n.data_ptr()), _VP(lam.data_ptr()),
+                                              _VP(dL_dtau.data_ptr())))
+
+    def fields_adjoint(self, tube, state, dfields, lam):
+        """Writes dL/df of a loss on the fields of `state` into tube's rows of lam."""
+        assert dfields.element_size() == 8 and dfields.is_contiguous() and dfields.shape[0] == 10
+        self._check(self.lib.rlb_fields_adjoint(self.h, tube, _VP(state.data_ptr()), _VP(dfields.data_ptr()),
+                                                dfields.shape[1], _VP(lam.data_ptr())))
+
+    def initial_state_adjoint(self, tube, lam0):
+        gl, gr = np.zeros(3), np.zeros(3)
+        self._check(self.lib.rlb_initial_state_adjoint(self.h, tube, _VP(lam0.data_ptr()), gl.ctypes.data_as(_DP),
+                                                       gr.ctypes.data_as(_DP)))
+        return gl, gr
+
+    Lattice.adjoint_step = adjoint_step
+    Lattice.fields_adjoint = fields_adjoint
+    Lattice.initial_state_adjoint = initial_state_adjoint
+
+
+_lattice_adjoint_methods()
 
 
 def device_copy(dst, src, nbytes: int, stream=None):
