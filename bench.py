@@ -1,18 +1,28 @@
 """Benchmark of the relativistic lattice Boltzmann step on one MI355X.
 
-Workload (default): the large Sod tube -- N_x = 2^20 cells, Q = 64 x 4
-quadrature points, tau = 1e-2, synthetic Sod initial states -- advanced by
-full SSP-RK3 steps.  The headline is the FP32 form (FP32 stencil and
-relaxation, Kahan-compensated FP32 moment sums, FP64 Landau matching); the
-FP64 form is timed beside it.
+Headline workload: the large Sod tube -- N_x = 2^20 cells, Q = 64 x 4
+quadrature points, tau = 1e-2, synthetic Sod initial states (the paper's
+left/right states) -- advanced by full SSP-RK3 steps in the FP32 form (FP32
+stencil and relaxation, Kahan-compensated FP32 moment sums, FP64 Landau
+matching).  A "step" is one full time step (three stage launches) of the
+whole tube.  Beside it, on the same line:
+  fp64        the FP64 form on the same tube, and the FP32-vs-FP64 error table
+              (max and L2 relative errors of e, v, T^{mu nu}) after the run;
+  batched     4096 seeded tubes of uneven size, order and tau in one launch
+              per stage, schedule chosen by the autotuner, replayed from a
+              hipGraph;
+  adjoint     gradient of the profile loss of the 4096-cell, Q = 32 x 3 tube
+              over 2000 steps (forward + sqrt(N)-checkpointed backward);
+  ballistic   the 2^22-cell, Q = 256 x 4 tube at tau = 1e3 (FP32);
+  roofline    of the stage kernel: algorithmic bytes per launch over its mean
+              duration, timed with HIP events on the launch stream;
+  cpu_baseline the CPU FP64 oracle on a bounded sample of the headline tube.
 
-Prints ONE JSON line: metric, value (cell x quadrature-point updates per
-second), the roofline of the stage kernel (algorithmic bytes per launch over
-its average duration, timed with HIP events on the launch stream), the CPU
-oracle timed on a bounded sample of the same workload, and the FP64 figures.
+Prints ONE JSON line.  Inputs are resident in HBM before every timed region.
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -21,79 +31,174 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+SOD_L, SOD_R = (1.0, 1.0, 0.0), (0.1, 0.125, 0.0)
 
 
-def stage_bytes_per_step(nx, Q, rsize):
+def step_bytes(tubes, rsize):
     """Algorithmic HBM bytes of one SSP-RK3 step (three stage launches).
 
-    Stage 1 reads f^n and writes f1; stages 2 and 3 read their input and f^n
-    and write their output: 8 accesses per point.  Each stage also reads and
-    writes the five FP64 moments of every cell (80 bytes per cell).
+    Per point: stage 1 reads f^n and writes f1; stages 2 and 3 read their input
+    and f^n and write their output: 8 accesses.  Per cell and stage the five
+    FP64 moments are read and written (80 bytes).
     """
-    return 8 * nx * Q * rsize + 3 * 80 * nx
+    return sum(8 * t.nx * t.Q * rsize + 3 * 80 * t.nx for t in tubes)
 
 
-def time_path(precision, params, steps, warmup, schedule=None):
+def timed_steps(lat, steps):
     import torch
-    from paper_1608_03004_amd import Lattice, Tube
-    lat = Lattice([Tube(**params)], precision=precision)
-    if schedule:
-        lat.set_schedule(**schedule)
-    lat.set_initial_state((1.0, 1.0, 0.0), (0.1, 0.125, 0.0))
-    lat.step(warmup)
-    lat.check()
-    stream = lat.stream
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    start.record(stream)
+    start.record(lat.stream)
     lat.step(steps)
-    stop.record(stream)
+    stop.record(lat.stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ev_ms = start.elapsed_time(stop)
+    return wall, start.elapsed_time(stop) * 1e-3
+
+
+def roofline(tubes, rsize, steps, event_s):
+    launch_s = event_s / (3 * steps)
+    bytes_launch = step_bytes(tubes, rsize) / 3
+    achieved = bytes_launch / launch_s / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                bytes_per_launch=int(bytes_launch), launch_us=round(launch_s * 1e6, 2))
+
+
+def leg_single(precision, params, steps, warmup, schedule=None):
+    from paper_1608_03004_amd import Lattice, Tube
+    tube = Tube(**params)
+    lat = Lattice([tube], precision=precision)
+    if schedule:
+        lat.set_schedule(**schedule)
+    lat.set_initial_state(SOD_L, SOD_R)
+    lat.step(warmup)
     lat.check()
+    wall, ev = timed_steps(lat, steps)
     fields = lat.moments(0)
-    Q = params["q_xi"] * params["q_p"]
-    nx = params["nx"]
     rsize = 4 if precision == "fp32" else 8
-    launch_ms = ev_ms / (3 * steps)
-    bytes_launch = stage_bytes_per_step(nx, Q, rsize) / 3
-    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
-    out = dict(
-        value=nx * Q * steps / wall,
-        ms_per_step=1e3 * wall / steps,
-        event_ms_per_step=ev_ms / steps,
-        roofline=dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                      frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                      bytes_per_launch=int(bytes_launch), launch_us=round(launch_ms * 1e3, 2)),
-        e_min=float(fields[5].min()),
-    )
+    out = dict(value=tube.nx * tube.Q * steps / wall, ms_per_step=1e3 * wall / steps,
+               roofline=roofline([tube], rsize, steps, ev), schedule=lat.get_schedule())
+    return out, fields, lat
+
+
+def error_table(f32, f64):
+    """Max and L2 relative errors (normwise per field) of FP32 against FP64."""
+    import numpy as np
+    names = dict(e=5, v=7, T00=2, T0z=3, Tzz=4, N0=0, n=6)
+    out = {}
+    for name, k in names.items():
+        d = f32[k] - f64[k]
+        s = max(np.abs(f64[k]).max(), 1e-300)
+        out[name] = dict(max=float(np.abs(d).max() / s), l2=float(np.sqrt(np.mean(d * d)) / s))
+    return out
+
+
+def leg_batched(steps, tune=True):
+    import torch
+    import workloads
+    from paper_1608_03004_amd import Lattice, Tube
+    from paper_1608_03004_amd import autotune
+    w = workloads.sod_batched()
+    tubes = [Tube(**t) for t in w["tubes"]]
+    lat = Lattice(tubes, precision="fp32")
+    lat.set_initial_states(w["left"], w["right"])
+    lat.step(1)
+    sched, timings = (autotune.tune(lat, steps=3, use_cache=False) if tune else (None, {}))
+    lat.set_initial_states(w["left"], w["right"])
+    lat.step(2)
+    lat.check()
+    wall, ev = timed_steps(lat, steps)
+    lat.check()
+    pts = sum(t.nx * t.Q for t in tubes)
+    best = sorted(timings.values())[:1]
+    out = dict(value=pts * steps / wall, unit="cell*quad-point updates/s", ms_per_step=1e3 * wall / steps,
+               steps=steps, tubes=len(tubes), points_per_step=pts, schedule=lat.get_schedule(),
+               roofline=roofline(tubes, 4, steps, ev),
+               autotune_candidates=len(timings),
+               workload="sod_batched: 4096 tubes, numpy default_rng(0): N_x~U{256..8192}, "
+                        "Q_xi~U{8,16,32,64,128}, Q_p=3, log tau~U[ln1e-4,ln10], "
+                        "log(P_L/P_R)~U[ln2,ln100], n_L/n_R~U[1,10], FP32")
     del lat
     torch.cuda.empty_cache()
     return out
 
 
-def cpu_baseline(params, target_s=10.0):
-    """The CPU FP64 oracle on a bounded sample: the same Q and tau on a
-    2^16-cell sub-tube, timed over whole steps (about 10 s of CPU work)."""
+def leg_adjoint(precision, nsteps=2000):
+    import torch
+    import workloads
+    from paper_1608_03004_amd import Lattice, Tube
+    from paper_1608_03004_amd.autograd import SodProfile
+    w = workloads.sod_adjoint()
+    p = dict(w["tubes"][0])
+    p["dt"] = 0.5 / p["nx"]
+    lat = Lattice([Tube(**p)], precision=precision, adjoint=True)
+    f64, dev = torch.float64, lat.device
+    tg = w["target"]
+    # target profile from the forward at (tau, P_L) = (0.05, 1.5)
+    with torch.no_grad():
+        target = SodProfile.apply(torch.tensor(tg["tau"], dtype=f64), torch.tensor(tg["P_L"], dtype=f64),
+                                  torch.tensor(tg["n_L"], dtype=f64), torch.tensor(0.1, dtype=f64),
+                                  torch.tensor(0.125, dtype=f64), lat, nsteps, 0).clone()
+    st = w["start"]
+    theta = [torch.tensor(v, dtype=f64, device=dev, requires_grad=True) for v in (st["tau"], st["P_L"], st["n_L"])]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e = SodProfile.apply(*theta, torch.tensor(0.1, dtype=f64, device=dev), torch.tensor(0.125, dtype=f64, device=dev),
+                         lat, nsteps, 0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss = torch.sum((e - target) ** 2) / p["nx"]
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    grads = [float(x.grad) for x in theta]
+    out = dict(adjoint_steps_per_s=nsteps / (t2 - t1), forward_steps_per_s=nsteps / (t1 - t0),
+               backward_s=t2 - t1, steps=nsteps, checkpoint_every=math.ceil(math.sqrt(nsteps)),
+               grad_tau=grads[0], grad_P_L=grads[1], grad_n_L=grads[2], loss=float(loss.detach()),
+               workload="sod_adjoint: N_x=4096, Q=32x3, 2000 steps, dt=0.5 dz, start (tau,P_L,n_L)=(0.02,1,1), "
+                        "target from (0.05,1.5,1)")
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def leg_ballistic(steps, warmup=2):
+    import numpy as np
+    import torch
+    from paper_1608_03004_amd import Lattice, Tube
+    tube = Tube(nx=1 << 22, q_xi=256, q_p=4, tau=1e3)
+    lat = Lattice([tube], precision="fp32")
+    lat.set_initial_state(SOD_L, SOD_R)
+    lat.step(warmup)
+    wall, ev = timed_steps(lat, steps)
+    lat.check()
+    out = dict(value=tube.nx * tube.Q * steps / wall, ms_per_step=1e3 * wall / steps, steps=steps,
+               roofline=roofline([tube], 4, steps, ev),
+               workload="sod_ballistic: N_x=2^22, Q=256x4, tau=1e3, FP32")
+    del lat
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(params, target_s=12.0):
+    """The CPU FP64 oracle on a bounded sample: the headline tube's Q and tau on
+    a sub-tube of 2^16 cells, timed over whole steps (about 10 s of CPU work)."""
     from oracle import oracle as O
     nx = 1 << 16
-    t = O.Tube(nx=nx, q_xi=params["q_xi"], q_p=params["q_p"], tau=params["tau"])
-    F = O.init(t, (1.0, 1.0, 0.0), (0.1, 0.125, 0.0))
+    t = O.Tube(nx=nx, q_xi=params["q_xi"], q_p=params["q_p"], tau=params["tau"], dt=0.5 / params["nx"])
+    F = O.init(t, SOD_L, SOD_R)
     t0 = time.perf_counter()
     F = O.step(t, F, 1)
     one = time.perf_counter() - t0
-    extra = max(0, min(4, int(target_s / max(one, 1e-3)) - 1))
+    n = max(1, min(40, int(target_s / max(one, 1e-3))))
     t0 = time.perf_counter()
-    if extra:
-        F = O.step(t, F, extra)
-    el = time.perf_counter() - t0
-    steps, secs = (extra, el) if extra else (1, one)
-    pts = nx * t.Q * steps
-    return dict(value=pts / secs, unit="cell*quad-point updates/s", cores=O.num_threads(), kind="oracle",
-                sample=f"FP64 oracle, {nx} cells x Q={t.Q} ({params['q_xi']}x{params['q_p']}), "
-                       f"tau={params['tau']}, {steps} step(s), {secs:.1f} s")
+    F = O.step(t, F, n)
+    secs = time.perf_counter() - t0
+    return dict(value=nx * t.Q * n / secs, unit="cell*quad-point updates/s", cores=O.num_threads(), kind="oracle",
+                sample=f"FP64 oracle on {nx} cells x Q={t.Q} ({params['q_xi']}x{params['q_p']}), tau={params['tau']}, "
+                       f"{n} steps in {secs:.1f} s (the headline tube's per-point work on 1/16 of its cells)")
 
 
 def main():
@@ -102,17 +207,24 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--nx", type=int, default=1 << 20)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--fp64", type=int, default=1, help="also time the FP64 path")
+    ap.add_argument("--tile", type=int, default=256)
+    ap.add_argument("--legs", default="fp64,batched,adjoint,ballistic,cpu",
+                    help="comma-separated extra legs (fp64, batched, adjoint, ballistic, cpu) or 'none'")
+    ap.add_argument("--batched-steps", type=int, default=50)
+    ap.add_argument("--ballistic-steps", type=int, default=20)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1); the multi-GPU "
+                                   "slab decomposition is a design, not built"}))
         sys.exit(2)
+    legs = set() if args.legs == "none" else set(args.legs.split(","))
     import torch
     torch.cuda.set_device(0)
     params = dict(nx=args.nx, q_xi=64, q_p=4, tau=1e-2)
-    r32 = time_path("fp32", params, args.steps, args.warmup)
-    r64 = time_path("fp64", params, args.steps, args.warmup) if args.fp64 else None
+    sched = dict(tile=args.tile)
+    r32, f32, lat = leg_single("fp32", params, args.steps, args.warmup, sched)
+    del lat
+    torch.cuda.empty_cache()
     line = {
         "metric": "cell*quad-point updates/s (FP32 vs FP64) + % HBM roofline; adjoint steps/s",
         "value": r32["value"],
@@ -127,14 +239,24 @@ def main():
         "dtype": "fp32",
         "data": "synthetic",
         "config": {"workload": "sod_large: Sod tube, N_x=2^20, Q=64x4 (Gauss-Legendre x Gauss-Laguerre), "
-                               "tau=1e-2, FP32 with Kahan moments and FP64 Landau",
-                   "nx": params["nx"], "q_xi": 64, "q_p": 4, "tau": 1e-2},
+                               "tau=1e-2, FP32 stencil/relaxation, Kahan FP32 moments, FP64 Landau",
+                   "nx": params["nx"], "q_xi": 64, "q_p": 4, "tau": 1e-2, "schedule": r32["schedule"]},
         "roofline": r32["roofline"],
     }
-    if r64:
+    if "fp64" in legs:
+        r64, f64, lat = leg_single("fp64", params, args.steps, args.warmup, sched)
+        del lat
+        torch.cuda.empty_cache()
         line["fp64"] = dict(value=r64["value"], ms_per_step=r64["ms_per_step"], roofline=r64["roofline"],
                             speedup_fp32_over_fp64=r32["value"] / r64["value"])
-    if not args.no_cpu:
+        line["fp32_vs_fp64_error"] = dict(after_steps=args.steps + args.warmup, fields=error_table(f32, f64))
+    if "batched" in legs:
+        line["batched"] = leg_batched(args.batched_steps)
+    if "adjoint" in legs:
+        line["adjoint"] = dict(fp64=leg_adjoint("fp64"), fp32=leg_adjoint("fp32"))
+    if "ballistic" in legs:
+        line["ballistic"] = leg_ballistic(args.ballistic_steps)
+    if "cpu" in legs:
         line["cpu_baseline"] = cpu_baseline(params)
     print(json.dumps(line), flush=True)
 

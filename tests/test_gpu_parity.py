@@ -222,3 +222,38 @@ def test_full_size_sod_large_fp32_window(torch_cuda):
 def test_full_size_ballistic_fp32_window(torch_cuda):
     # N_x = 2^22, Q = 256 x 4, tau = 1e3 (the ballistic stress configuration), FP32
     _window_check(dict(nx=1 << 22, q_xi=256, q_p=4, tau=1e3), "fp32", 2, tol=1e-5)
+
+
+def test_autotuner_restores_state_and_keeps_results(torch_cuda, tmp_path):
+    from paper_1608_03004_amd import autotune
+    import workloads
+    w = workloads.sod_batched(ntubes=40, seed=3)
+    plist = [dict(t, nx=min(t["nx"], 700)) for t in w["tubes"]]
+    ref = _lattice(plist)
+    ref.set_initial_states(w["left"], w["right"])
+    ref.step(6)
+    lat = _lattice(plist)
+    lat.set_initial_states(w["left"], w["right"])
+    lat.step(3)
+    best, timings = autotune.tune(lat, steps=2, cache_path=str(tmp_path / "cache.json"))
+    assert best in [dict(c) for c in autotune.CANDIDATES] and len(timings) == len(autotune.CANDIDATES)
+    lat.step(3)
+    for k in (0, 17, 39):
+        assert np.array_equal(lat.state_array(k), ref.state_array(k))
+    # cached choice is reused without timing
+    best2, _ = autotune.tune(lat, cache_path=str(tmp_path / "cache.json"))
+    assert best2 == best
+
+
+def test_batched_seeded_tubes_against_oracle(torch_cuda):
+    # a few tubes of the seeded batched draw, shortened, against the oracle
+    import workloads
+    w = workloads.sod_batched(ntubes=12, seed=0)
+    plist = [dict(t, nx=min(t["nx"], 600)) for t in w["tubes"]]
+    lat = _lattice(plist, precision="fp32", schedule=dict(tile=128, persistent=1, blocks_per_cu=2, graph_steps=4))
+    lat.set_initial_states(w["left"], w["right"])
+    lat.step(12)
+    for k in (0, 5, 11):
+        F, ref = _oracle_run(plist[k], w["left"][k], w["right"][k], 12)
+        errs = field_errors(lat.moments(k), ref)
+        assert max(e[0] for e in errs.values()) < 1e-5, (k, errs)
