@@ -182,6 +182,31 @@ def leg_ballistic(steps, warmup=2):
     return out
 
 
+def leg_copy(nbytes=1 << 30, reps=5):
+    """Plain device-to-device copy through the library's copy kernel: the
+    practical HBM ceiling, and the calibration of the HBM byte counters."""
+    import torch
+    from paper_1608_03004_amd import rlb
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    rlb.device_copy(dst, src, nbytes)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stream = torch.cuda.current_stream()
+    start.record(stream)
+    for _ in range(reps):
+        rlb.device_copy(dst, src, nbytes)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    s = start.elapsed_time(stop) * 1e-3 / reps
+    ok = bool(torch.equal(dst, src))
+    del src, dst
+    torch.cuda.empty_cache()
+    return dict(bytes_read=nbytes, bytes_written=nbytes, us_per_copy=round(s * 1e6, 2),
+                achieved_GBs=round(2 * nbytes / s / 1e9, 1), frac_of_peak=round(2 * nbytes / s / 1e9 / HBM_PEAK_GBS, 4),
+                verified=ok)
+
+
 def cpu_baseline(params, target_s=12.0):
     """The CPU FP64 oracle on a bounded sample: the headline tube's Q and tau on
     a sub-tube of 2^16 cells, timed over whole steps (about 10 s of CPU work)."""
@@ -208,8 +233,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--nx", type=int, default=1 << 20)
     ap.add_argument("--tile", type=int, default=256)
-    ap.add_argument("--legs", default="fp64,batched,adjoint,ballistic,cpu",
-                    help="comma-separated extra legs (fp64, batched, adjoint, ballistic, cpu) or 'none'")
+    ap.add_argument("--legs", default="fp64,batched,adjoint,ballistic,copy,cpu",
+                    help="comma-separated extra legs (fp64, batched, adjoint, ballistic, copy, cpu) or 'none'")
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--ballistic-steps", type=int, default=20)
     args = ap.parse_args()
@@ -256,6 +281,8 @@ def main():
         line["adjoint"] = dict(fp64=leg_adjoint("fp64"), fp32=leg_adjoint("fp32"))
     if "ballistic" in legs:
         line["ballistic"] = leg_ballistic(args.ballistic_steps)
+    if "copy" in legs:
+        line["copy"] = leg_copy()
     if "cpu" in legs:
         line["cpu_baseline"] = cpu_baseline(params)
     print(json.dumps(line), flush=True)

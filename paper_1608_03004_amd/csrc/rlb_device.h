@@ -133,26 +133,38 @@ __device__ inline void feq_coefficients(Real n, Real T, Real gamma, Real u, Real
 }
 
 // Fifth-order WENO (Jiang-Shu) value at the face between v3 and v4 from the
-// upwind-ordered values v1..v5.  The three nonlinear weights
-// alpha_r = d_r/(eps+beta_r)^2 are normalised with a single division by
-// multiplying numerator and denominator by prod_r (eps+beta_r)^2.
+// upwind-ordered values v1..v5:  H = sum_r w_r q_r with the candidate values
+// q_r of the three 3-point stencils and the weights w_r = a_r / sum(a),
+// a_r = d_r / (eps + beta_r)^2, d = (1/10, 6/10, 3/10).  Evaluated with one
+// reciprocal: numerator and denominator are multiplied by prod_r (eps+beta_r)^2
+// and by 6, the smoothness indicators are scaled by 4 (eps4 = 4 eps), and the
+// constants d_r and 6 are folded into the candidate combinations.
+__device__ inline float weno_recip(float num, float den) { return num * __builtin_amdgcn_rcpf(den); }
+__device__ inline double weno_recip(double num, double den) {
+  double r = __builtin_amdgcn_rcp(den);
+  r = fma(r, fma(-den, r, 1.0), r);
+  return num * r;
+}
+
 template <typename Real>
-__device__ inline Real weno5(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps) {
-  const Real q0 = (Real(2) * v1 - Real(7) * v2 + Real(11) * v3) * Real(1.0 / 6.0);
-  const Real q1 = (-v2 + Real(5) * v3 + Real(2) * v4) * Real(1.0 / 6.0);
-  const Real q2 = (Real(2) * v3 + Real(5) * v4 - v5) * Real(1.0 / 6.0);
+__device__ inline Real weno5(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps4) {
+  const Real c = Real(13.0 / 3.0);
   const Real t0 = v1 - Real(2) * v2 + v3, s0 = v1 - Real(4) * v2 + Real(3) * v3;
   const Real t1 = v2 - Real(2) * v3 + v4, s1 = v2 - v4;
   const Real t2 = v3 - Real(2) * v4 + v5, s2 = Real(3) * v3 - Real(4) * v4 + v5;
-  const Real c13 = Real(13.0 / 12.0), c14 = Real(0.25);
-  const Real e0 = eps + c13 * t0 * t0 + c14 * s0 * s0;
-  const Real e1 = eps + c13 * t1 * t1 + c14 * s1 * s1;
-  const Real e2 = eps + c13 * t2 * t2 + c14 * s2 * s2;
+  const Real e0 = (c * t0) * t0 + (s0 * s0 + eps4);
+  const Real e1 = (c * t1) * t1 + (s1 * s1 + eps4);
+  const Real e2 = (c * t2) * t2 + (s2 * s2 + eps4);
   const Real A = e0 * e0, B = e1 * e1, C = e2 * e2;
-  const Real a0 = Real(0.1) * (B * C), a1 = Real(0.6) * (A * C), a2 = Real(0.3) * (A * B);
-  return fast_div(a0 * q0 + a1 * q1 + a2 * q2, a0 + a1 + a2);
+  const Real w0 = B * C, w1 = A * C, w2 = A * B;
+  // d_r * 6 q_r
+  const Real p0 = Real(0.2) * v1 - Real(0.7) * v2 + Real(1.1) * v3;
+  const Real p1 = Real(-0.6) * v2 + Real(3.0) * v3 + Real(1.2) * v4;
+  const Real p2 = Real(0.6) * v3 + Real(1.5) * v4 - Real(0.3) * v5;
+  const Real num = w0 * p0 + w1 * p1 + w2 * p2;
+  const Real den = Real(0.6) * w0 + Real(3.6) * w1 + Real(1.8) * w2;
+  return weno_recip(num, den);
 }
-
 
 // ---------------------------------------------------------------------------
 // Reverse-mode derivatives (hand-written) of the per-cell maps above.

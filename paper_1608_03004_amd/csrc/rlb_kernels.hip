@@ -29,9 +29,41 @@
 namespace rlb {
 namespace {
 
-constexpr int kChunk = 8;  // quadrature points staged in LDS per barrier round
+
 
 using namespace dev;
+
+// Points per chunk: 8 in FP32; 4 in FP64, where registers are scarcer.
+template <typename Real>
+constexpr int chunk_points() {
+  return sizeof(Real) == 4 ? 8 : 4;
+}
+
+// Moment sums of one radial node's row of values, in the order the stage
+// kernel's epilogue uses (plain sums within chunks of chunk_points() points,
+// compensated across chunks), so that records computed from a stored state
+// are bitwise equal to the records written while the state was produced.
+template <typename Real, typename Get>
+__device__ inline void row_moments(const Real* jtab, int qx, Get get, double& s0, double& s1, double& s2) {
+  constexpr int CH = chunk_points<Real>();
+  Acc<Real> a0, a1, a2;
+  for (int j0 = 0; j0 < qx; j0 += CH) {
+    Real p0 = Real(0), p1 = Real(0), p2 = Real(0);
+    for (int c = 0; c < CH && j0 + c < qx; ++c) {
+      const Real* J = jtab + (j0 + c) * kJStride;
+      const Real v = get(j0 + c);
+      p0 += J[1] * v;
+      p1 += J[2] * v;
+      p2 += J[3] * v;
+    }
+    a0.add(p0);
+    a1.add(p1);
+    a2.add(p2);
+  }
+  s0 = a0.value();
+  s1 = a1.value();
+  s2 = a2.value();
+}
 
 // WENO value at the face between tile positions k+2 and k+3 (left face of the
 // cell stored at k+3), upwinded by the sign of xi.
@@ -52,40 +84,72 @@ __device__ inline void load_record(const double* rec, int64_t ldx, int x, double
 // ---------------------------------------------------------------------------
 // Stage kernel
 // ---------------------------------------------------------------------------
-// Loads of one chunk: the tile's own cells for kChunk points (rows clamped to
-// the last valid point, so every lane always issues the same loads) and, in
-// wave 0, the 6-cell halo of all kChunk points with one instruction.
-template <typename Real, int TILE>
+// XCD-aware work distribution.  Workgroups are dispatched round-robin over the
+// 8 XCDs (workgroup b runs on XCD b % 8), and each XCD has its own L2.  The
+// work list keeps a tube's tiles in ascending order, so handing each XCD one
+// contiguous run of the list puts neighbouring tiles -- which read each
+// other's 3-cell halos -- on the same L2.  v is the workgroup's virtual index
+// (blockIdx.x + k * gridDim.x with gridDim.x a multiple of 8, or plain
+// blockIdx.x); the map is a bijection on [0, n).
+constexpr int kXcds = 8;
+__device__ inline int xcd_item(int v, int n) {
+  const int q = n / kXcds, r = n % kXcds;
+  const int x = v % kXcds, k = v / kXcds;
+  return x * q + min(x, r) + k;
+}
+
+// Streaming loads of the distribution (read once per stage).
+template <typename Real>
+__device__ inline Real stream_load(const Real* p) {
+#ifdef RLB_NT_LOADS
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
+// Loads of one chunk: the tile's own cells for CH points (rows clamped to the
+// last valid point, so every lane always issues the same loads) and, in
+// wave 0, the 6-cell halo of all CH points with one instruction.
+template <typename Real, int CH>
 struct ChunkLoads {
-  Real f[kChunk];
+  Real f[CH];
   Real halo;
 };
 
-template <typename Real, int TILE>
+template <typename Real, int TILE, int CH>
 __device__ inline void issue_chunk(const Real* fin, int64_t ldx, int qx, int i, int j0, int xc, int t, int x0,
-                                   int nx, ChunkLoads<Real, TILE>& L) {
+                                   int nx, ChunkLoads<Real, CH>& L) {
 #pragma unroll
-  for (int c = 0; c < kChunk; ++c) {
+  for (int c = 0; c < CH; ++c) {
     const int j = min(j0 + c, qx - 1);
-    const Real* row = fin + int64_t(i * qx + j) * ldx;
-    L.f[c] = row[xc];
+    L.f[c] = stream_load(fin + int64_t(i * qx + j) * ldx + xc);
   }
   if (t < 64) {  // wave 0: lane h + 6c loads halo cell h of chunk point c
-    const int c = min(t / 6, kChunk - 1), h = t % 6;
+    const int c = min(t / 6, CH - 1), h = t % 6;
     const int j = min(j0 + c, qx - 1);
     const int hx = h < 3 ? max(x0 - 3 + h, 0) : min(x0 + TILE + (h - 3), nx - 1);
     L.halo = fin[int64_t(i * qx + j) * ldx + hx];
   }
 }
 
-template <typename Real, int TILE, int QPT, int NVT, bool HAS_FN>
+// Moment sums over one radial node: plain sums within a chunk, Kahan-
+// compensated across chunks in FP32 (plain FP64 sums in the FP64 form).
+template <typename Real>
+struct Moments3 {
+  Acc<Real> a0, a1, a2;
+};
+
+template <typename Real, int TILE, int QPT, int NVT, bool HAS_FN, int CH>
 __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
-  __shared__ Real tile[kChunk][TILE + 6];
-  __shared__ Real faces[kChunk][TILE + 1];
+  __shared__ Real tile[CH][TILE + 6];
+  __shared__ Real faces[CH][TILE + 1];
   const int t = threadIdx.x;
   const cptr<WorkItem> items = as_const(a.items);
   const cptr<TubeDev> tubes = as_const(a.tubes);
-  for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
+  const bool xcd_map = (gridDim.x % kXcds) == 0 || gridDim.x == unsigned(a.nitems);
+  for (int v = blockIdx.x; v < a.nitems; v += gridDim.x) {
+    const int item = xcd_map ? xcd_item(v, a.nitems) : v;
     const int wtube = items[item].tube, wx0 = items[item].x0;
     const cptr<TubeDev> tbp = tubes + wtube;
     const int nx = tbp->nx, qx = tbp->qx, qp = tbp->qp;
@@ -102,10 +166,8 @@ __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
     const cptr<double> itab = as_const(a.itab) + int64_t(tbp->irow) * kIStride;
 
     // first chunk's loads go out before the per-cell prologue
-    const int nci = (qx + kChunk - 1) / kChunk;
-    const int nchunks = qp * nci;
-    ChunkLoads<Real, TILE> cur;
-    issue_chunk<Real, TILE>(fin, ldx, qx, 0, 0, xc, t, x0, nx, cur);
+    ChunkLoads<Real, CH> cur;
+    issue_chunk<Real, TILE, CH>(fin, ldx, qx, 0, 0, xc, t, x0, nx, cur);
 
     // 1-2. moments of the stage input -> Landau frame (FP64)
     double m[5];
@@ -122,94 +184,91 @@ __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
                                      tbp->nv, itab, as_const(a.aux), a.aux_pairs, D);
     const double tau_inv = tbp->tau_inv;
     const Real g0 = Real(M.gamma * tau_inv), g1 = Real(M.u * tau_inv);
-    const Real dt = Real(tbp->dt), dz_inv = Real(tbp->dz_inv), eps = Real(tbp->weno_eps);
+    const Real dt = Real(tbp->dt), dz_inv = Real(tbp->dz_inv), eps4 = Real(4.0 * tbp->weno_eps);
     const int stage = a.stage;
+    // out = cn f^n + cs f_in + cs dt L
     const Real cn = stage == 1 ? Real(0) : (stage == 2 ? Real(0.75) : Real(1.0 / 3.0));
     const Real cs = stage == 1 ? Real(1) : (stage == 2 ? Real(0.25) : Real(2.0 / 3.0));
+    const Real cdt = cs * dt;
 
     double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    Acc<Real> acc0, acc1, acc2;
-    for (int k = 0; k < nchunks; ++k) {
-      const int i = k / nci;
-      const int j0 = (k - i * nci) * kChunk;
-      const int cj = min(kChunk, qx - j0);
-      // prefetch the next chunk (the last chunk re-loads itself)
-      ChunkLoads<Real, TILE> nxt;
-      {
-        const int kn = min(k + 1, nchunks - 1);
-        const int in = kn / nci;
-        issue_chunk<Real, TILE>(fin, ldx, qx, in, (kn - in * nci) * kChunk, xc, t, x0, nx, nxt);
-      }
 #pragma unroll
-      for (int c = 0; c < kChunk; ++c) tile[c][t + 3] = cur.f[c];
-      if (t < 6 * kChunk) {
-        const int c = t / 6, h = t % 6;
-        tile[c][h < 3 ? h : TILE + h] = cur.halo;
-      }
-      __syncthreads();
-      // f^n of this chunk, consumed after the faces
-      Real nr[kChunk];
+    for (int i = 0; i < QPT; ++i) {
+      if (i < qp) {
+        Moments3<Real> acc;
+        for (int j0 = 0; j0 < qx; j0 += CH) {
+          const int cj = min(CH, qx - j0);
+          // prefetch the next chunk (the next radial node's first chunk at the
+          // end of this one; the very last chunk re-loads itself)
+          ChunkLoads<Real, CH> nxt;
+          {
+            int in = i, jn = j0 + CH;
+            if (jn >= qx) { in = i + 1; jn = 0; }
+            if (in >= qp) { in = i; jn = j0; }
+            issue_chunk<Real, TILE, CH>(fin, ldx, qx, in, jn, xc, t, x0, nx, nxt);
+          }
 #pragma unroll
-      for (int c = 0; c < kChunk; ++c) {
-        if (HAS_FN) {
-          const int j = min(j0 + c, qx - 1);
-          nr[c] = fn[int64_t(i * qx + j) * ldx + xc];
-        } else {
-          nr[c] = Real(0);
+          for (int c = 0; c < CH; ++c) tile[c][t + 3] = cur.f[c];
+          if (t < 6 * CH) {
+            const int c = t / 6, h = t % 6;
+            tile[c][h < 3 ? h : TILE + h] = cur.halo;
+          }
+          __syncthreads();
+          // f^n of this chunk, consumed after the faces
+          Real nr[CH];
+#pragma unroll
+          for (int c = 0; c < CH; ++c) {
+            if (HAS_FN) {
+              const int j = min(j0 + c, qx - 1);
+              nr[c] = stream_load(fn + int64_t(i * qx + j) * ldx + xc);
+            } else {
+              nr[c] = Real(0);
+            }
+          }
+#pragma unroll
+          for (int c = 0; c < CH; ++c) {
+            const bool pos = jtab[min(j0 + c, qx - 1) * kJStride] >= Real(0);
+            faces[c][t] = face_value(tile[c], t, pos, eps4);
+          }
+          if (t < CH) {  // the tile's right-most face, one chunk point per lane
+            const bool pos = jtab[min(j0 + t, qx - 1) * kJStride] >= Real(0);
+            faces[t][TILE] = face_value(tile[t], TILE, pos, eps4);
+          }
+          __syncthreads();
+          Real p0 = Real(0), p1 = Real(0), p2 = Real(0);
+#pragma unroll
+          for (int c = 0; c < CH; ++c) {
+            if (c < cj) {
+              const cptr<Real> J = jtab + (j0 + c) * kJStride;
+              const Real xi = J[0];
+              Real feq = D[i][0];
+#pragma unroll
+              for (int kk = 1; kk <= NVT; ++kk) feq += D[i][kk] * J[4 + kk];
+              const Real fr = cur.f[c];
+              const Real adv = (faces[c][t + 1] - faces[c][t]) * (-xi * dz_inv);
+              const Real rate = g0 - xi * g1;
+              const Real L = adv - rate * (fr - feq);
+              const Real out = HAS_FN ? cdt * L + (cs * fr + cn * nr[c]) : fr + dt * L;
+              if (valid) fout[int64_t(i * qx + j0 + c) * ldx + x] = out;
+              p0 += J[1] * out;
+              p1 += J[2] * out;
+              p2 += J[3] * out;
+            }
+          }
+          acc.a0.add(p0);
+          acc.a1.add(p1);
+          acc.a2.add(p2);
+          __syncthreads();
+          cur = nxt;
         }
-      }
-#pragma unroll
-      for (int c = 0; c < kChunk; ++c) {
-        const bool pos = jtab[min(j0 + c, qx - 1) * kJStride] >= Real(0);
-        faces[c][t] = face_value(tile[c], t, pos, eps);
-      }
-      if (t < kChunk) {  // the tile's right-most face, one chunk point per lane
-        const bool pos = jtab[min(j0 + t, qx - 1) * kJStride] >= Real(0);
-        faces[t][TILE] = face_value(tile[t], TILE, pos, eps);
-      }
-      __syncthreads();
-      // coefficients of this radial node
-      Real d[NVT + 1];
-#pragma unroll
-      for (int kk = 0; kk <= NVT; ++kk) {
-        d[kk] = D[0][kk];
-#pragma unroll
-        for (int ii = 1; ii < QPT; ++ii)
-          if (ii == i) d[kk] = D[ii][kk];
-      }
-#pragma unroll
-      for (int c = 0; c < kChunk; ++c) {
-        if (c < cj) {
-          const cptr<Real> J = jtab + (j0 + c) * kJStride;
-          const Real xi = J[0];
-          Real feq = Real(0);
-#pragma unroll
-          for (int kk = 0; kk <= NVT; ++kk) feq += d[kk] * J[4 + kk];
-          const Real adv = -xi * dz_inv * (faces[c][t + 1] - faces[c][t]);
-          const Real rate = g0 - xi * g1;
-          const Real fr = cur.f[c];
-          const Real L = adv - rate * (fr - feq);
-          const Real out = HAS_FN ? cn * nr[c] + cs * (fr + dt * L) : fr + dt * L;
-          if (valid) fout[int64_t(i * qx + j0 + c) * ldx + x] = out;
-          acc0.add(J[1] * out);
-          acc1.add(J[2] * out);
-          acc2.add(J[3] * out);
-        }
-      }
-      if (j0 + kChunk >= qx) {  // last chunk of radial node i: fold its sums
         const cptr<double> I = itab + i * kIStride;
-        const double s0 = acc0.value(), s1 = acc1.value(), s2 = acc2.value();
+        const double s0 = acc.a0.value(), s1 = acc.a1.value(), s2 = acc.a2.value();
         mom[0] += I[2] * s0;
         mom[1] += I[2] * s1;
         mom[2] += I[3] * s0;
         mom[3] += I[3] * s1;
         mom[4] += I[3] * s2;
-        acc0 = Acc<Real>();
-        acc1 = Acc<Real>();
-        acc2 = Acc<Real>();
       }
-      __syncthreads();
-      cur = nxt;
     }
     if (valid) {
       double* ro = a.rec_out + tbp->rec_off;
@@ -245,24 +304,22 @@ __global__ __launch_bounds__(TILE) void init_kernel(InitArgs<Real> a) {
 #pragma unroll
     for (int i = 0; i < QPT; ++i) {
       if (i < tb.qp) {
-        Acc<Real> acc0, acc1, acc2;
+        Real* row = f + int64_t(i * tb.qx) * tb.ldx + x;
         for (int j = 0; j < tb.qx; ++j) {
           const Real* J = jtab + j * kJStride;
-          Real F = Real(0);
+          Real F = D[i][0];
 #pragma unroll
-          for (int k = 0; k <= NVT; ++k) F += D[i][k] * J[4 + k];
-          f[int64_t(i * tb.qx + j) * tb.ldx + x] = F;
-          acc0.add(J[1] * F);
-          acc1.add(J[2] * F);
-          acc2.add(J[3] * F);
+          for (int k = 1; k <= NVT; ++k) F += D[i][k] * J[4 + k];
+          row[int64_t(j) * tb.ldx] = F;
         }
+        double s0, s1, s2;
+        row_moments<Real>(jtab, tb.qx, [&](int j) { return row[int64_t(j) * tb.ldx]; }, s0, s1, s2);
         const double* I = itab + i * kIStride;
-        const double a0 = acc0.value(), a1 = acc1.value(), a2 = acc2.value();
-        mom[0] += I[2] * a0;
-        mom[1] += I[2] * a1;
-        mom[2] += I[3] * a0;
-        mom[3] += I[3] * a1;
-        mom[4] += I[3] * a2;
+        mom[0] += I[2] * s0;
+        mom[1] += I[2] * s1;
+        mom[2] += I[3] * s0;
+        mom[3] += I[3] * s1;
+        mom[4] += I[3] * s2;
       }
     }
     double* rec = a.rec + tb.rec_off;
@@ -287,21 +344,15 @@ __global__ __launch_bounds__(256) void moments_kernel(const TubeDev* tubes, cons
       const Real* f = f_all + tb.f_off;
       double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
       for (int i = 0; i < tb.qp; ++i) {
-        Acc<Real> acc0, acc1, acc2;
-        for (int j = 0; j < tb.qx; ++j) {
-          const Real* J = jtab + j * kJStride;
-          const Real F = f[int64_t(i * tb.qx + j) * tb.ldx + x];
-          acc0.add(J[1] * F);
-          acc1.add(J[2] * F);
-          acc2.add(J[3] * F);
-        }
+        const Real* row = f + int64_t(i * tb.qx) * tb.ldx + x;
+        double s0, s1, s2;
+        row_moments<Real>(jtab, tb.qx, [&](int j) { return row[int64_t(j) * tb.ldx]; }, s0, s1, s2);
         const double* I = itab + i * kIStride;
-        const double a0 = acc0.value(), a1 = acc1.value(), a2 = acc2.value();
-        mom[0] += I[2] * a0;
-        mom[1] += I[2] * a1;
-        mom[2] += I[3] * a0;
-        mom[3] += I[3] * a1;
-        mom[4] += I[3] * a2;
+        mom[0] += I[2] * s0;
+        mom[1] += I[2] * s1;
+        mom[2] += I[3] * s0;
+        mom[3] += I[3] * s1;
+        mom[4] += I[3] * s2;
       }
       double* rec = rec_all + tb.rec_off;
       for (int c = 0; c < 5; ++c) rec[int64_t(c) * tb.ldx + x] = mom[c];
@@ -361,10 +412,11 @@ __global__ __launch_bounds__(256) void copy_kernel(uint4* __restrict__ dst, cons
 template <typename Real, int TILE, int QPT, int NVT>
 hipError_t launch_stage_t(const LaunchShape& ls, const void* args, hipStream_t s) {
   const StageArgs<Real>& a = *static_cast<const StageArgs<Real>*>(args);
+  constexpr int CH = chunk_points<Real>();
   if (a.stage == 1)
-    hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, false>), dim3(ls.grid), dim3(TILE), 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, false, CH>), dim3(ls.grid), dim3(TILE), 0, s, a);
   else
-    hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, true>), dim3(ls.grid), dim3(TILE), 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, true, CH>), dim3(ls.grid), dim3(TILE), 0, s, a);
   return hipGetLastError();
 }
 
