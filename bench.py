@@ -57,12 +57,36 @@ def timed_steps(lat, steps):
     return wall, start.elapsed_time(stop) * 1e-3
 
 
-def roofline(tubes, rsize, steps, event_s):
+def kernel_source_sha1():
+    import hashlib
+    h = hashlib.sha1()
+    for f in ("rlb_kernels.hip", "rlb_device.h", "rlb_internal.h"):
+        with open(os.path.join(ROOT, "paper_1608_03004_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(precision):
+    """HBM bytes per stage launch of the headline tube from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE runs (calibrated on the copy kernel), or
+    None when the kernel sources changed since those counters were taken."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha1") != kernel_source_sha1() or precision not in t:
+        return None
+    return int(t[precision]["traffic_bytes_per_launch"])
+
+
+def roofline(tubes, rsize, steps, event_s, traffic=None):
     launch_s = event_s / (3 * steps)
     bytes_launch = step_bytes(tubes, rsize) / 3
     achieved = bytes_launch / launch_s / 1e9
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic,
                 bytes_per_launch=int(bytes_launch), launch_us=round(launch_s * 1e6, 2))
 
 
@@ -78,8 +102,9 @@ def leg_single(precision, params, steps, warmup, schedule=None):
     wall, ev = timed_steps(lat, steps)
     fields = lat.moments(0)
     rsize = 4 if precision == "fp32" else 8
+    traffic = measured_traffic(precision) if (tube.nx, tube.q_xi, tube.q_p) == (1 << 20, 64, 4) else None
     out = dict(value=tube.nx * tube.Q * steps / wall, ms_per_step=1e3 * wall / steps,
-               roofline=roofline([tube], rsize, steps, ev), schedule=lat.get_schedule())
+               roofline=roofline([tube], rsize, steps, ev, traffic), schedule=lat.get_schedule())
     return out, fields, lat
 
 
@@ -233,6 +258,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--nx", type=int, default=1 << 20)
     ap.add_argument("--tile", type=int, default=256)
+    ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"),
+                    help="form of the headline tube (fp64 is for profiling runs; the headline is fp32)")
     ap.add_argument("--legs", default="fp64,batched,adjoint,ballistic,copy,cpu",
                     help="comma-separated extra legs (fp64, batched, adjoint, ballistic, copy, cpu) or 'none'")
     ap.add_argument("--batched-steps", type=int, default=50)
@@ -247,7 +274,7 @@ def main():
     torch.cuda.set_device(0)
     params = dict(nx=args.nx, q_xi=64, q_p=4, tau=1e-2)
     sched = dict(tile=args.tile)
-    r32, f32, lat = leg_single("fp32", params, args.steps, args.warmup, sched)
+    r32, f32, lat = leg_single(args.precision, params, args.steps, args.warmup, sched)
     del lat
     torch.cuda.empty_cache()
     line = {
@@ -261,7 +288,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp32",
+        "dtype": args.precision,
         "data": "synthetic",
         "config": {"workload": "sod_large: Sod tube, N_x=2^20, Q=64x4 (Gauss-Legendre x Gauss-Laguerre), "
                                "tau=1e-2, FP32 stencil/relaxation, Kahan FP32 moments, FP64 Landau",

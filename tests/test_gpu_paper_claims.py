@@ -1,0 +1,75 @@
+"""The paper's own qualitative claims (section Numerical results), reproduced
+on the GPU path at the paper's sizes.  Loose by nature: the figures carry no
+data and some run settings are unstated (the resolution of Fig. 2 is taken as
+2000 nodes here)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_setup.json")))
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    return torch
+
+
+def test_hydrodynamic_shock_is_a_few_nodes_wide(torch_cuda):
+    # tau = 1e-4, dt = 0.5e-4, L_z = 10^4, N_p = 2, N_v = 5, Q_xi = 6:
+    # "the width is equal to around 6-7 grid nodes"
+    from paper_1608_03004_amd import experiments as E
+    run = GOLDEN["hydro_run"]["value"]
+    res = E.hydro(nx=run["L_z"], t_end=0.2)
+    print(f"[hydro] {res}", flush=True)
+    lo, hi = GOLDEN["hydro_shock_width_nodes"]["value"]
+    assert lo - 3 <= res["shock_width_nodes"] <= hi + 5
+    # the post-shock density approaches the ideal P = e/3 value 0.2885 (hydro limit)
+    from oracle import analytic as A
+    st = A.riemann_star((1.0, 1.0, 0.0), (0.1, 0.125, 0.0))
+    assert abs(res["post_shock_n"] - st["nR"]) < 0.05 * st["nR"]
+
+
+def test_quadrature_order_four_converges_in_the_hydrodynamic_regime(torch_cuda):
+    # "In the hydrodynamic regime (tau = 1e-4), we found that Q_xi = 4 is
+    # sufficient to achieve convergence" (error below 1% against Q_xi = 200).
+    from paper_1608_03004_amd import experiments as E
+    g = GOLDEN["convergence_Qxi_hydro"]
+    res = E.error_vs_order(nx=2000, t_end=0.25, taus=(g["tau"],), orders=(g["value"],),
+                           ref_order=g["reference_Qxi"])
+    eps = res[g["tau"]][g["value"]]
+    print(f"[convergence] Q_xi=4, tau=1e-4: eps={eps:.4f}", flush=True)
+    assert eps < g["threshold"]
+
+
+def test_required_order_grows_with_tau(torch_cuda):
+    from paper_1608_03004_amd import experiments as E
+    res = E.error_vs_order(nx=1000, t_end=0.25, taus=(1e-4, 1.0), orders=(4, 16), ref_order=200)
+    print(f"[convergence] {res}", flush=True)
+    assert res[1.0][4] > res[1e-4][4]   # larger tau needs more quadrature points
+    assert res[1.0][16] < res[1.0][4]   # and more points help there
+
+
+def test_ballistic_profile_at_high_order_overlaps_the_analytic_one(torch_cuda):
+    # Fig. 1b: at t = 0.25 the Q_xi = 200 profile and eq. ballistic overlap.
+    from paper_1608_03004_amd import experiments as E
+    from oracle import analytic as A
+    nx = 4000
+    res = E.ballistic(nx=nx, t_end=GOLDEN["ballistic_time"]["value"], orders=(8, 200))
+    z = -0.5 + (np.arange(nx) + 0.5) / nx
+    dn = GOLDEN["delta_n"]["value"]
+    err = {}
+    for q, r in res.items():
+        nb = A.n_ballistic(z, r["t"])
+        err[q] = float(np.max(np.abs(r["Nabs"] - nb)) / dn)
+    print(f"[ballistic] max |N| - n_bal over Delta n: {err}", flush=True)
+    # the discrete-velocity staircase alone deviates by ~0.0043 Delta n at Q_xi = 200
+    assert err[200] < 0.02
+    assert err[8] > 5 * err[200]
