@@ -332,7 +332,7 @@ R weno5(R v1, R v2, R v3, R v4, R v5, double eps) {
 }
 
 // Open (zero-gradient outflow) boundary: the three ghost cells on each side
-// repeat the edge cell [reading of "open boundary conditions"].
+// repeat the edge cell [reading of the open boundaries the paper names].
 inline int64_t clampx(int64_t x, int64_t nx) { return x < 0 ? 0 : (x >= nx ? nx - 1 : x); }
 
 // Weight-free numerical flux value H at face x+1/2 for node row F (length nx),
@@ -377,8 +377,8 @@ void rhs(const Tables& tb, const oracle_tube& t, R tau_inv, const R* F, R* out) 
 }
 
 // Third-order strong-stability-preserving Runge-Kutta step of Shu and Osher
-// (the "nonlinearly stable 3rd order Runge-Kutta" of section "Numerical
-// results") [reading]:
+// (the third-order TVD Runge-Kutta integrator named in section Numerical
+// results) [reading]:
 //   F1 = F + dt L(F);  F2 = 3/4 F + 1/4 (F1 + dt L(F1));
 //   F' = 1/3 F + 2/3 (F2 + dt L(F2)).
 template <class R>

@@ -119,7 +119,8 @@ rlb_status validate(const rlb_tube_desc& d, int k, std::string& msg) {
     msg = buf;
     return RLB_ERR_INVALID_ARG;
   };
-  if (d.nx < 8 || d.nx > (1 << 28)) return bad("nx must be in [8, 2^28]");
+  // the stage kernel addresses a chunk of rows with 32-bit byte offsets
+  if (d.nx < 8 || d.nx > (1 << 26)) return bad("nx must be in [8, 2^26]");
   if (d.q_xi < 1 || d.q_xi > 4096) return bad("q_xi must be in [1, 4096]");
   if (d.q_p < 1 || d.q_p > kMaxQp) return bad("q_p must be in [1, 8]");
   if (d.n_v < 0 || d.n_v > kMaxNv) return bad("n_v must be in [0, 7]");

@@ -135,10 +135,16 @@ __device__ inline void feq_coefficients(Real n, Real T, Real gamma, Real u, Real
 // Fifth-order WENO (Jiang-Shu) value at the face between v3 and v4 from the
 // upwind-ordered values v1..v5:  H = sum_r w_r q_r with the candidate values
 // q_r of the three 3-point stencils and the weights w_r = a_r / sum(a),
-// a_r = d_r / (eps + beta_r)^2, d = (1/10, 6/10, 3/10).  Evaluated with one
-// reciprocal: numerator and denominator are multiplied by prod_r (eps+beta_r)^2
-// and by 6, the smoothness indicators are scaled by 4 (eps4 = 4 eps), and the
-// constants d_r and 6 are folded into the candidate combinations.
+// a_r = d_r / (eps + beta_r)^2, d = (1/10, 6/10, 3/10).
+//
+// Evaluated in the first differences a = v2-v1, b = v3-v2, c = v4-v3,
+// d = v5-v4 of the stencil, with t = (b-a, c-b, d-c) its second differences:
+//   4 beta_r = 13/3 t_r^2 + s_r^2,   s = (3b - a, b + c, d - 3c),
+//   q_r = v3 + P_r / 6,              P = (3b + 2 t0, b + 2c, 3c - t2).
+// Numerator and denominator are multiplied by prod_r (eps + beta_r)^2 (so one
+// reciprocal remains; eps4 = 4 eps) and by 10/6:
+//   H = v3 + (w0 P0/6 + w1 P1 + w2 P2/2) / (w0 + 6 w1 + 3 w2),
+//   w0 = e1^2 e2^2, w1 = e0^2 e2^2, w2 = e0^2 e1^2,  e_r = 4 (eps + beta_r).
 __device__ inline float weno_recip(float num, float den) { return num * __builtin_amdgcn_rcpf(den); }
 __device__ inline double weno_recip(double num, double den) {
   double r = __builtin_amdgcn_rcp(den);
@@ -148,22 +154,21 @@ __device__ inline double weno_recip(double num, double den) {
 
 template <typename Real>
 __device__ inline Real weno5(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps4) {
-  const Real c = Real(13.0 / 3.0);
-  const Real t0 = v1 - Real(2) * v2 + v3, s0 = v1 - Real(4) * v2 + Real(3) * v3;
-  const Real t1 = v2 - Real(2) * v3 + v4, s1 = v2 - v4;
-  const Real t2 = v3 - Real(2) * v4 + v5, s2 = Real(3) * v3 - Real(4) * v4 + v5;
-  const Real e0 = (c * t0) * t0 + (s0 * s0 + eps4);
-  const Real e1 = (c * t1) * t1 + (s1 * s1 + eps4);
-  const Real e2 = (c * t2) * t2 + (s2 * s2 + eps4);
+  const Real a = v2 - v1, b = v3 - v2, c = v4 - v3, d = v5 - v4;
+  const Real t0 = b - a, t1 = c - b, t2 = d - c;
+  const Real s0 = Real(3) * b - a, s1 = b + c, s2 = d - Real(3) * c;
+  const Real k = Real(13.0 / 3.0);
+  const Real e0 = (k * t0) * t0 + (s0 * s0 + eps4);
+  const Real e1 = (k * t1) * t1 + (s1 * s1 + eps4);
+  const Real e2 = (k * t2) * t2 + (s2 * s2 + eps4);
   const Real A = e0 * e0, B = e1 * e1, C = e2 * e2;
   const Real w0 = B * C, w1 = A * C, w2 = A * B;
-  // d_r * 6 q_r
-  const Real p0 = Real(0.2) * v1 - Real(0.7) * v2 + Real(1.1) * v3;
-  const Real p1 = Real(-0.6) * v2 + Real(3.0) * v3 + Real(1.2) * v4;
-  const Real p2 = Real(0.6) * v3 + Real(1.5) * v4 - Real(0.3) * v5;
-  const Real num = w0 * p0 + w1 * p1 + w2 * p2;
-  const Real den = Real(0.6) * w0 + Real(3.6) * w1 + Real(1.8) * w2;
-  return weno_recip(num, den);
+  const Real R0 = Real(0.5) * b + Real(1.0 / 3.0) * t0;  // P0 / 6
+  const Real R1 = b + Real(2) * c;                         // P1
+  const Real R2 = Real(1.5) * c - Real(0.5) * t2;         // P2 / 2
+  const Real num = w0 * R0 + w1 * R1 + w2 * R2;
+  const Real den = w0 + Real(6) * w1 + Real(3) * w2;
+  return v3 + weno_recip(num, den);
 }
 
 // ---------------------------------------------------------------------------

@@ -23,6 +23,8 @@
 // The outflow boundary (zero-gradient ghosts) is index clamping at load time.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "rlb_device.h"
 #include "rlb_internal.h"
 
@@ -36,7 +38,11 @@ using namespace dev;
 // Points per chunk: 8 in FP32; 4 in FP64, where registers are scarcer.
 template <typename Real>
 constexpr int chunk_points() {
+#ifdef RLB_FP32_CHUNK
+  return sizeof(Real) == 4 ? RLB_FP32_CHUNK : 4;
+#else
   return sizeof(Real) == 4 ? 8 : 4;
+#endif
 }
 
 // Moment sums of one radial node's row of values, in the order the stage
@@ -65,12 +71,23 @@ __device__ inline void row_moments(const Real* jtab, int qx, Get get, double& s0
   s2 = a2.value();
 }
 
-// WENO value at the face between tile positions k+2 and k+3 (left face of the
-// cell stored at k+3), upwinded by the sign of xi.
+// LDS layout of a chunk: value (c, p) -- chunk point c, tile position p --
+// at plane[c / V][p][c % V], V = 16 / sizeof(Real), so that one lane's values
+// of V consecutive chunk points are one 16-byte word and consecutive lanes
+// touch consecutive words (bank-conflict free 128-bit accesses).  Every read
+// of the face and update phases is then a fixed offset from a per-lane base.
 template <typename Real>
-__device__ inline Real face_value(const Real* row, int k, bool positive, Real eps) {
-  if (positive) return weno5(row[k], row[k + 1], row[k + 2], row[k + 3], row[k + 4], eps);
-  return weno5(row[k + 5], row[k + 4], row[k + 3], row[k + 2], row[k + 1], eps);
+struct LdsVec {
+  static constexpr int V = 16 / int(sizeof(Real));
+  typedef Real type __attribute__((ext_vector_type(V)));
+};
+
+// WENO value at the face between tile positions k+2 and k+3 (left face of the
+// cell stored at k+3) from the six values r[k..k+5], upwinded by the sign of xi.
+template <typename Real>
+__device__ inline Real face_value(const Real r[6], bool positive, Real eps) {
+  if (positive) return weno5(r[0], r[1], r[2], r[3], r[4], eps);
+  return weno5(r[5], r[4], r[3], r[2], r[1], eps);
 }
 
 __device__ inline void raise_flag(unsigned* flag, unsigned bits) { atomicOr(flag, bits); }
@@ -103,19 +120,69 @@ __device__ inline int xcd_item(int v, int n) {
   return (k / kXcdRun) * S + x * kXcdRun + (k % kXcdRun);
 }
 
-// Streaming loads of the distribution (read once per stage).
-template <typename Real>
-__device__ inline Real stream_load(const Real* p) {
-#ifdef RLB_NT_LOADS
-  return __builtin_nontemporal_load(p);
-#else
-  return *p;
-#endif
+// Raw buffer resources.  In the chunk loop every access is a scalar base
+// (per chunk), a scalar row offset and a 32-bit per-lane byte offset, so the
+// loads and stores carry no per-lane 64-bit address arithmetic; the resource's
+// size bounds every access to the chunk's rows.
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // word 3 of a raw 32-bit-format resource (gfx950)
+
+__device__ inline Rsrc make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), kRsrcWord3);
 }
 
-// Loads of one chunk: the tile's own cells for CH points (rows clamped to the
-// last valid point, so every lane always issues the same loads) and, in
-// wave 0, the 6-cell halo of all CH points with one instruction.
+#ifndef RLB_LOAD_AUX
+#define RLB_LOAD_AUX 0
+#endif
+#ifndef RLB_FN_AUX
+#define RLB_FN_AUX 2
+#endif
+#ifndef RLB_STORE_AUX
+#define RLB_STORE_AUX 2
+#endif
+// Cache policies: 0 = default, 2 = non-temporal (streaming).
+constexpr int kLoadAux = RLB_LOAD_AUX, kFnAux = RLB_FN_AUX, kStoreAux = RLB_STORE_AUX;
+
+template <typename Real>
+struct BufIO;
+template <>
+struct BufIO<float> {
+  template <int AUX = kLoadAux>
+  static __device__ inline float load(Rsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), AUX));
+  }
+  static __device__ inline void store(float v, Rsrc r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(voff), int(soff), kStoreAux);
+  }
+};
+template <>
+struct BufIO<double> {
+  using V2 = uint32_t __attribute__((ext_vector_type(2)));
+  template <int AUX = kLoadAux>
+  static __device__ inline double load(Rsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), AUX));
+  }
+  static __device__ inline void store(double v, Rsrc r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, int(voff), int(soff), kStoreAux);
+  }
+};
+
+// The CH rows of chunk (i, j0) of one tube's distribution: rows i*qx + j0 + c,
+// with rows past the last point repeating the last row (so every lane always
+// issues the same loads).  `row_bytes` = ldx * sizeof(Real).
+template <typename Real, int CH>
+struct ChunkRows {
+  Rsrc r;
+  int last;  // index of the last valid row of the chunk
+  __device__ inline ChunkRows(const Real* tube_f, int64_t ldx, uint32_t row_bytes, int qx, int i, int j0) {
+    r = make_rsrc(tube_f + int64_t(i * qx + j0) * ldx, uint32_t(CH) * row_bytes);
+    last = min(CH - 1, qx - 1 - j0);
+  }
+  __device__ inline uint32_t soff(int c, uint32_t row_bytes) const { return uint32_t(min(c, last)) * row_bytes; }
+};
+
+// Loads of one chunk: the tile's own cells for CH points and, in wave 0, the
+// 6-cell halo of all CH points with one instruction.
 template <typename Real, int CH>
 struct ChunkLoads {
   Real f[CH];
@@ -123,18 +190,16 @@ struct ChunkLoads {
 };
 
 template <typename Real, int TILE, int CH>
-__device__ inline void issue_chunk(const Real* fin, int64_t ldx, int qx, int i, int j0, int xc, int t, int x0,
-                                   int nx, ChunkLoads<Real, CH>& L) {
+__device__ inline void issue_chunk(const Real* tube_f, int64_t ldx, uint32_t row_bytes, int qx, int i, int j0,
+                                   uint32_t vx, int t, int x0, int nx, ChunkLoads<Real, CH>& L) {
+  const ChunkRows<Real, CH> rows(tube_f, ldx, row_bytes, qx, i, j0);
 #pragma unroll
-  for (int c = 0; c < CH; ++c) {
-    const int j = min(j0 + c, qx - 1);
-    L.f[c] = stream_load(fin + int64_t(i * qx + j) * ldx + xc);
-  }
+  for (int c = 0; c < CH; ++c) L.f[c] = BufIO<Real>::load(rows.r, vx, rows.soff(c, row_bytes));
   if (t < 64) {  // wave 0: lane h + 6c loads halo cell h of chunk point c
     const int c = min(t / 6, CH - 1), h = t % 6;
-    const int j = min(j0 + c, qx - 1);
     const int hx = h < 3 ? max(x0 - 3 + h, 0) : min(x0 + TILE + (h - 3), nx - 1);
-    L.halo = fin[int64_t(i * qx + j) * ldx + hx];
+    const uint32_t off = uint32_t(min(c, rows.last)) * row_bytes + uint32_t(hx) * uint32_t(sizeof(Real));
+    L.halo = BufIO<Real>::load(rows.r, off, 0);
   }
 }
 
@@ -147,8 +212,12 @@ struct Moments3 {
 
 template <typename Real, int TILE, int QPT, int NVT, bool HAS_FN, int CH>
 __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
-  __shared__ Real tile[CH][TILE + 6];
-  __shared__ Real faces[CH][TILE + 1];
+  constexpr int V = LdsVec<Real>::V, NH = CH / V;
+  static_assert(CH % V == 0, "a chunk is a whole number of 16-byte LDS words");
+  using Vec = typename LdsVec<Real>::type;
+  __shared__ __attribute__((aligned(16))) Real tile[NH][TILE + 6][V];
+  __shared__ __attribute__((aligned(16))) Real faces[NH][TILE + 1][V];
+  __shared__ double mom[5][TILE];
   const int t = threadIdx.x;
   const cptr<WorkItem> items = as_const(a.items);
   const cptr<TubeDev> tubes = as_const(a.tubes);
@@ -159,10 +228,12 @@ __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
     const cptr<TubeDev> tbp = tubes + wtube;
     const int nx = tbp->nx, qx = tbp->qx, qp = tbp->qp;
     const int64_t ldx = tbp->ldx;
+    const uint32_t row_bytes = uint32_t(ldx) * uint32_t(sizeof(Real));
     const int x0 = wx0;
     const int x = x0 + t;
     const bool valid = x < nx;
     const int xc = valid ? x : nx - 1;
+    const uint32_t vx = uint32_t(xc) * uint32_t(sizeof(Real));
     const int64_t f_off = tbp->f_off;
     const Real* fin = a.fin + f_off;
     const Real* fn = a.fn + f_off;
@@ -171,8 +242,8 @@ __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
     const cptr<double> itab = as_const(a.itab) + int64_t(tbp->irow) * kIStride;
 
     // first chunk's loads go out before the per-cell prologue
-    ChunkLoads<Real, CH> cur;
-    issue_chunk<Real, TILE, CH>(fin, ldx, qx, 0, 0, xc, t, x0, nx, cur);
+    ChunkLoads<Real, CH> bufA, bufB;
+    issue_chunk<Real, TILE, CH>(fin, ldx, row_bytes, qx, 0, 0, vx, t, x0, nx, bufA);
 
     // 1-2. moments of the stage input -> Landau frame (FP64)
     double m[5];
@@ -183,102 +254,181 @@ __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
     if (valid && !M.ok) raise_flag(a.flag, kFlagNonphysical);
     if (valid && fabs(M.v) > 0.95) raise_flag(a.flag, kFlagFastFlow);
 
-    // 3. equilibrium coefficients and relaxation rate (gamma - xi u)/tau
+    // 3. equilibrium coefficients
     Real D[QPT][NVT + 1];
     feq_coefficients<Real, QPT, NVT>(Real(M.n), Real(M.T), Real(M.gamma), Real(M.u), Real(tbp->T0), qp, tbp->np,
                                      tbp->nv, itab, as_const(a.aux), a.aux_pairs, D);
-    const double tau_inv = tbp->tau_inv;
-    const Real g0 = Real(M.gamma * tau_inv), g1 = Real(M.u * tau_inv);
-    const Real dt = Real(tbp->dt), dz_inv = Real(tbp->dz_inv), eps4 = Real(4.0 * tbp->weno_eps);
+    // out = cn f^n + cs f_in + cs dt L,  L = -xi/dz (F_+ - F_-) - (gamma - xi u)/tau (f - f^eq)
     const int stage = a.stage;
-    // out = cn f^n + cs f_in + cs dt L
     const Real cn = stage == 1 ? Real(0) : (stage == 2 ? Real(0.75) : Real(1.0 / 3.0));
     const Real cs = stage == 1 ? Real(1) : (stage == 2 ? Real(0.25) : Real(2.0 / 3.0));
-    const Real cdt = cs * dt;
+    const Real dt = Real(tbp->dt), dz_inv = Real(tbp->dz_inv), cdt = cs * dt;
+    const Real g0 = Real(M.gamma * tbp->tau_inv), g1 = Real(M.u * tbp->tau_inv);
+    const Real eps4 = Real(4.0 * tbp->weno_eps);
 
-    double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // One chunk: stage `cur` in LDS, prefetch the next chunk into `nxt`,
+    // WENO faces, update, moment sums.
+    auto chunk = [&](ChunkLoads<Real, CH>& cur, ChunkLoads<Real, CH>& nxt, int i, int j0, const Real* Dc,
+                     Moments3<Real>& acc) {
+      // f^n of this chunk (consumed after the faces), issued before the prefetch
+      Real nr[CH];
+      if (HAS_FN) {
+        const ChunkRows<Real, CH> rows(fn, ldx, row_bytes, qx, i, j0);
 #pragma unroll
-    for (int i = 0; i < QPT; ++i) {
-      if (i < qp) {
-        Moments3<Real> acc;
-        for (int j0 = 0; j0 < qx; j0 += CH) {
-          const int cj = min(CH, qx - j0);
-          // prefetch the next chunk (the next radial node's first chunk at the
-          // end of this one; the very last chunk re-loads itself)
-          ChunkLoads<Real, CH> nxt;
-          {
-            int in = i, jn = j0 + CH;
-            if (jn >= qx) { in = i + 1; jn = 0; }
-            if (in >= qp) { in = i; jn = j0; }
-            issue_chunk<Real, TILE, CH>(fin, ldx, qx, in, jn, xc, t, x0, nx, nxt);
-          }
+        for (int c = 0; c < CH; ++c) nr[c] = BufIO<Real>::template load<kFnAux>(rows.r, vx, rows.soff(c, row_bytes));
+      }
+      {  // next chunk: the next radial node's first at the end of a node; the
+         // very last chunk re-loads itself
+        int in = i, jn = j0 + CH;
+        if (jn >= qx) { in = i + 1; jn = 0; }
+        if (in >= qp) { in = i; jn = j0; }
+        issue_chunk<Real, TILE, CH>(fin, ldx, row_bytes, qx, in, jn, vx, t, x0, nx, nxt);
+      }
 #pragma unroll
-          for (int c = 0; c < CH; ++c) tile[c][t + 3] = cur.f[c];
-          if (t < 6 * CH) {
-            const int c = t / 6, h = t % 6;
-            tile[c][h < 3 ? h : TILE + h] = cur.halo;
-          }
-          __syncthreads();
-          // f^n of this chunk, consumed after the faces
-          Real nr[CH];
+      for (int h = 0; h < NH; ++h) {
+        Vec w;
 #pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            if (HAS_FN) {
-              const int j = min(j0 + c, qx - 1);
-              nr[c] = stream_load(fn + int64_t(i * qx + j) * ldx + xc);
-            } else {
-              nr[c] = Real(0);
-            }
-          }
+        for (int e = 0; e < V; ++e) w[e] = cur.f[h * V + e];
+        *reinterpret_cast<Vec*>(&tile[h][t + 3][0]) = w;
+      }
+      if (t < 6 * CH) {
+        const int c = t / 6, h = t % 6;
+        tile[c / V][h < 3 ? h : TILE + h][c % V] = cur.halo;
+      }
+      __syncthreads();
+      // WENO5 value at this lane's left face and, by CH
+      // lanes, at the tile's right-most face.  The six values at tile
+      // positions t..t+5 cover both upwind directions; the direction is a
+      // branch on the chunk's sign pattern, a wave-uniform bit mask from
+      // scalar table reads (all points of a chunk share the sign of xi except
+      // in the chunk that straddles xi = 0).
+      uint32_t pos_mask = 0;
 #pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            const bool pos = jtab[min(j0 + c, qx - 1) * kJStride] >= Real(0);
-            faces[c][t] = face_value(tile[c], t, pos, eps4);
-          }
-          if (t < CH) {  // the tile's right-most face, one chunk point per lane
-            const bool pos = jtab[min(j0 + t, qx - 1) * kJStride] >= Real(0);
-            faces[t][TILE] = face_value(tile[t], TILE, pos, eps4);
-          }
-          __syncthreads();
-          Real p0 = Real(0), p1 = Real(0), p2 = Real(0);
+      for (int c = 0; c < CH; ++c) pos_mask |= uint32_t(jtab[min(j0 + c, qx - 1) * kJStride] >= Real(0)) << c;
+      Real own[CH];
 #pragma unroll
-          for (int c = 0; c < CH; ++c) {
-            if (c < cj) {
+      for (int h = 0; h < NH; ++h) {
+        Vec rv[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) rv[k] = *reinterpret_cast<const Vec*>(&tile[h][t + k][0]);
+        const uint32_t hm = (pos_mask >> (h * V)) & ((1u << V) - 1u);
+        auto faces_of = [&](auto dir) {
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            Real r[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) r[k] = rv[k][e];
+            const bool pos = decltype(dir)::value == 1 ? true : decltype(dir)::value == 0 ? false : ((hm >> e) & 1u);
+            own[h * V + e] = face_value(r, pos, eps4);
+            __builtin_amdgcn_sched_barrier(0);  // one face at a time
+          }
+        };
+        if (hm == (1u << V) - 1u)
+          faces_of(std::integral_constant<int, 1>{});
+        else if (hm == 0)
+          faces_of(std::integral_constant<int, 0>{});
+        else
+          faces_of(std::integral_constant<int, 2>{});
+        __builtin_amdgcn_sched_barrier(0);
+      }
+#pragma unroll
+      for (int h = 0; h < NH; ++h) {
+        Vec w;
+#pragma unroll
+        for (int e = 0; e < V; ++e) w[e] = own[h * V + e];
+        *reinterpret_cast<Vec*>(&faces[h][t][0]) = w;
+      }
+      if (t < CH) {  // the tile's right-most face, one chunk point per lane
+        Real r[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) r[k] = tile[t / V][TILE + k][t % V];
+        faces[t / V][TILE][t % V] = face_value(r, (pos_mask >> t) & 1u, eps4);
+      }
+      __syncthreads();
+      const int cj = min(CH, qx - j0);
+      const ChunkRows<Real, CH> orow(fout, ldx, row_bytes, qx, i, j0);
+      auto update = [&](auto full) {
+        Real p0 = Real(0), p1 = Real(0), p2 = Real(0);
+#pragma unroll
+        for (int h = 0; h < NH; ++h) {
+          // this lane's cell values and faces for V chunk points, back from LDS
+          const Vec wf = *reinterpret_cast<const Vec*>(&tile[h][t + 3][0]);
+          const Vec wl = *reinterpret_cast<const Vec*>(&faces[h][t][0]);
+          const Vec wr = *reinterpret_cast<const Vec*>(&faces[h][t + 1][0]);
+#pragma unroll
+          for (int e = 0; e < V; ++e) {
+            const int c = h * V + e;
+            if (decltype(full)::value || c < cj) {
               const cptr<Real> J = jtab + (j0 + c) * kJStride;
-              const Real xi = J[0];
-              Real feq = D[i][0];
+              Real feq = Dc[0];
 #pragma unroll
-              for (int kk = 1; kk <= NVT; ++kk) feq += D[i][kk] * J[4 + kk];
-              const Real fr = cur.f[c];
-              const Real adv = (faces[c][t + 1] - faces[c][t]) * (-xi * dz_inv);
-              const Real rate = g0 - xi * g1;
-              const Real L = adv - rate * (fr - feq);
+              for (int kk = 1; kk <= NVT; ++kk) feq += Dc[kk] * J[4 + kk];
+              const Real fr = wf[e];
+              const Real df = fr - feq;
+              const Real adv = (wr[e] - wl[e]) * (-J[0] * dz_inv);
+              const Real rate = g0 - J[0] * g1;
+              const Real L = adv - rate * df;
+              // the RK combination of the stage input and f^n is formed first,
+              // so that a state with L = 0 is reproduced exactly
               const Real out = HAS_FN ? cdt * L + (cs * fr + cn * nr[c]) : fr + dt * L;
-              if (valid) fout[int64_t(i * qx + j0 + c) * ldx + x] = out;
+              if (valid) BufIO<Real>::store(out, orow.r, vx, uint32_t(c) * row_bytes);
               p0 += J[1] * out;
               p1 += J[2] * out;
               p2 += J[3] * out;
             }
           }
-          acc.a0.add(p0);
-          acc.a1.add(p1);
-          acc.a2.add(p2);
-          __syncthreads();
-          cur = nxt;
+          // keep the scheduler from hoisting the next plane's reads (bounds
+          // the live registers; occupancy hides the latency instead)
+          __builtin_amdgcn_sched_barrier(0);
         }
-        const cptr<double> I = itab + i * kIStride;
-        const double s0 = acc.a0.value(), s1 = acc.a1.value(), s2 = acc.a2.value();
-        mom[0] += I[2] * s0;
-        mom[1] += I[2] * s1;
-        mom[2] += I[3] * s0;
-        mom[3] += I[3] * s1;
-        mom[4] += I[3] * s2;
+        acc.a0.add(p0);
+        acc.a1.add(p1);
+        acc.a2.add(p2);
+      };
+      if (cj == CH)
+        update(std::true_type{});
+      else
+        update(std::false_type{});
+      __syncthreads();
+    };
+
+    // the five moment sums of this lane's cell live in LDS (registers are
+    // the scarce resource here); each lane only touches its own column
+#pragma unroll
+    for (int c = 0; c < 5; ++c) mom[c][t] = 0.0;
+    // runtime loop over radial nodes (the node's coefficient row is selected
+    // with uniform conditional moves); the chunk loop alternates the two
+    // register buffers so that no in-flight load is ever copied
+#pragma unroll 1
+    for (int i = 0; i < qp; ++i) {
+      Real Dc[NVT + 1];
+#pragma unroll
+      for (int k = 0; k <= NVT; ++k) {
+        Real d = D[0][k];
+#pragma unroll
+        for (int ii = 1; ii < QPT; ++ii) d = i == ii ? D[ii][k] : d;
+        Dc[k] = d;
       }
+      Moments3<Real> acc;
+      for (int j0 = 0; j0 < qx; j0 += 2 * CH) {
+        chunk(bufA, bufB, i, j0, Dc, acc);
+        if (j0 + CH < qx)
+          chunk(bufB, bufA, i, j0 + CH, Dc, acc);
+        else
+          bufA = bufB;  // odd number of chunks per node: the next node starts in A
+      }
+      const cptr<double> I = itab + i * kIStride;
+      const double s0 = acc.a0.value(), s1 = acc.a1.value(), s2 = acc.a2.value();
+      mom[0][t] += I[2] * s0;
+      mom[1][t] += I[2] * s1;
+      mom[2][t] += I[3] * s0;
+      mom[3][t] += I[3] * s1;
+      mom[4][t] += I[3] * s2;
     }
     if (valid) {
       double* ro = a.rec_out + tbp->rec_off;
 #pragma unroll
-      for (int c = 0; c < 5; ++c) ro[c * ldx + x] = mom[c];
+      for (int c = 0; c < 5; ++c) ro[c * ldx + x] = mom[c][t];
     }
   }
 }
