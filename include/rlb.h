@@ -68,7 +68,7 @@ typedef enum { RLB_FP64 = 0, RLB_FP32 = 1 } rlb_precision;
  * One shock tube, following the problem statement of the paper:
  *   grid      -- the unit-length domain of 1 x 1 x L_z nodes of section
  *                Numerical results: cell-centred cells on [z_min, z_max],
- *                dz = (z_max - z_min)/nx;
+ *                dz = (z_max - z_min)/nx, 8 <= nx <= 2^26;
  *   q_xi, q_p -- quadrature orders (section "Discretization of the momentum
  *                space"; Q_p = 3 suffices for N^mu and T^{mu nu}, section
  *                Riemann problem); q_p <= 8;

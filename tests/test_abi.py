@@ -42,6 +42,7 @@ def test_defaults_are_the_papers(lib):
 
 @pytest.mark.parametrize("bad,status", [
     (dict(nx=4), rlb.RLB_ERR_INVALID_ARG),
+    (dict(nx=(1 << 26) + 1), rlb.RLB_ERR_INVALID_ARG),              # chunk offsets are 32-bit
     (dict(q_p=9), rlb.RLB_ERR_INVALID_ARG),
     (dict(n_p=3, q_p=3), rlb.RLB_ERR_INVALID_ARG),
     (dict(q_p=2, n_p=1, n_v=5, q_xi=2), rlb.RLB_ERR_INVALID_ARG),   # q_xi too small for T^{mu nu}
