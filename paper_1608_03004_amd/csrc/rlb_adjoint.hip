@@ -10,7 +10,8 @@
 // with B_s the moment basis of point s and mu(x) = dR/dm^T K, obtained from a
 // reduction over the points of the cell followed by the adjoints of the
 // equilibrium projection and of the Landau matching.  Three kernels per stage:
-//   adj_reduce   one lane per cell: mu(x), the rate constants and d/dtau,
+//   adj_reduce   per cell (four waves share a cell's sums): mu(x), the rate
+//                constants and d/dtau,
 //   adj_faces    one lane per (point, face): WENO5 gradient times the face
 //                adjoint phi = -(xi/dz)(K_left - K_right),
 //   adj_combine  one lane per (point, cell): gathers the face contributions
@@ -27,56 +28,103 @@ namespace {
 
 using namespace dev;
 
+// adj_reduce: a block holds kRedCells cells (one per lane) and kRedGroups
+// groups of lanes (one wave each).  The groups split the quadrature points of
+// the reduction and the auxiliary node pairs of the projection's adjoint;
+// partial sums are combined through LDS in a fixed group order, so the result
+// is deterministic.
+constexpr int kRedCells = 64, kRedGroups = 4;
+
+// acc[d][lane] = sum over groups (in group order) of part[d]; every group
+// reads the same combined values afterwards.  Ends with a barrier.
+template <int N>
+__device__ inline void combine_groups(double (*acc)[kRedCells], const double* part, int grp, int lane) {
+  for (int g = 0; g < kRedGroups; ++g) {
+    if (grp == g) {
+#pragma unroll
+      for (int d = 0; d < N; ++d) acc[d][lane] = (g == 0) ? part[d] : acc[d][lane] + part[d];
+    }
+    __syncthreads();
+  }
+}
+
 template <typename Real, int QPT, int NVT>
-__global__ __launch_bounds__(256) void adj_reduce_kernel(AdjArgs<Real> a) {
+__global__ __launch_bounds__(kRedCells * kRedGroups) void adj_reduce_kernel(AdjArgs<Real> a) {
+  constexpr int ND = QPT * (NVT + 1);
+  __shared__ double acc[ND + 3][kRedCells];
+  const int lane = threadIdx.x % kRedCells, grp = threadIdx.x / kRedCells;
   const TubeDev& tb = a.tubes[a.tube];
-  const int y = blockIdx.x * blockDim.x + threadIdx.x;
-  if (y >= tb.nx) return;
+  const int nx = tb.nx;
+  const int y = blockIdx.x * kRedCells + lane;
+  const bool valid = y < nx;
+  const int yc = valid ? y : nx - 1;
   const int64_t ldx = tb.ldx;
   const int qx = tb.qx, qp = tb.qp;
   const cptr<Real> jtab = as_const(a.jtab) + int64_t(tb.jrow) * kJStride;
   const cptr<double> itab = as_const(a.itab) + int64_t(tb.irow) * kIStride;
   double m[5];
-  for (int c = 0; c < 5; ++c) m[c] = a.rec_g[tb.rec_off + c * ldx + y];
+  for (int c = 0; c < 5; ++c) m[c] = a.rec_g[tb.rec_off + c * ldx + yc];
   const Macro M = landau(m);
+
+  // 1. projection coefficients, evaluated exactly as the forward stage kernel
+  //    does (every group; f - f^eq is small, so the reduction below needs the
+  //    forward's f^eq to the last bit)
   Real D[QPT][NVT + 1];
   feq_coefficients<Real, QPT, NVT>(Real(M.n), Real(M.T), Real(M.gamma), Real(M.u), Real(tb.T0), qp, tb.np, tb.nv,
                                    itab, as_const(a.aux), a.aux_pairs, D);
+
+  // 2. reduction over the points (group grp takes j = grp, grp + G, ...)
   const double tau_inv = tb.tau_inv;
   const Real g0 = Real(M.gamma * tau_inv), g1 = Real(M.u * tau_inv);
   const Real* g = a.g + tb.f_off;
   const Real* K = a.K + tb.f_off;
-  double Gb = 0.0, Ub = 0.0, taup = 0.0;
-  double Db[QPT][NVT + 1];
+  double red[ND + 3];
 #pragma unroll
-  for (int i = 0; i < QPT; ++i)
-#pragma unroll
-    for (int k = 0; k <= NVT; ++k) Db[i][k] = 0.0;
+  for (int d = 0; d < ND + 3; ++d) red[d] = 0.0;
+  double& Gb = red[ND];
+  double& Ub = red[ND + 1];
+  double& taup = red[ND + 2];
 #pragma unroll
   for (int i = 0; i < QPT; ++i) {
     if (i < qp) {
-      for (int j = 0; j < qx; ++j) {
+#pragma unroll 4
+      for (int j = grp; j < qx; j += kRedGroups) {
         const cptr<Real> J = jtab + j * kJStride;
         const Real xi = J[0];
         const int64_t row = int64_t(i * qx + j) * ldx;
-        const double Kv = double(K[row + y]);
+        const double Kv = double(K[row + yc]);
         Real e = Real(0);
 #pragma unroll
         for (int k = 0; k <= NVT; ++k) e += D[i][k] * J[4 + k];
-        const double diff = double(g[row + y]) - double(e);
+        const double diff = double(g[row + yc]) - double(e);
         const double rho = double(g0 - xi * g1);
         Gb -= Kv * diff * tau_inv;
         Ub += Kv * double(xi) * diff * tau_inv;
         const double kr = Kv * rho;
 #pragma unroll
-        for (int k = 0; k <= NVT; ++k) Db[i][k] += kr * double(J[4 + k]);
+        for (int k = 0; k <= NVT; ++k) red[i * (NVT + 1) + k] += kr * double(J[4 + k]);
         taup += kr * tau_inv * diff;
       }
     }
   }
-  double nb = 0.0, Tb = 0.0, gb = Gb, ub = Ub;
-  feq_coefficients_adjoint<QPT, NVT>(M.n, M.T, M.gamma, M.u, tb.T0, qp, tb.np, tb.nv, itab, as_const(a.aux_d),
-                                     a.aux_pairs, Db, nb, Tb, gb, ub);
+  combine_groups<ND + 3>(acc, red, grp, lane);
+  double Db[QPT][NVT + 1];
+#pragma unroll
+  for (int i = 0; i < QPT; ++i)
+#pragma unroll
+    for (int k = 0; k <= NVT; ++k) Db[i][k] = acc[i * (NVT + 1) + k][lane];
+  const double Gb_all = acc[ND][lane], Ub_all = acc[ND + 1][lane], taup_all = acc[ND + 2][lane];
+  __syncthreads();  // acc is reused below
+
+  // 3. adjoint of the projection (the groups share the auxiliary pairs again)
+  double part[4] = {0.0, 0.0, 0.0, 0.0};  // prefb, rb, gamma-bar, u-bar
+  feq_adjoint_sums<QPT, NVT>(M.n, M.T, M.gamma, M.u, tb.T0, qp, tb.np, tb.nv, itab, as_const(a.aux_d), a.aux_pairs,
+                             grp, kRedGroups, Db, part[0], part[1], part[2], part[3]);
+  combine_groups<4>(acc, part, grp, lane);
+  if (grp != 0 || !valid) return;
+  double nb = 0.0, Tb = 0.0;
+  feq_adjoint_finish(M.n, M.T, tb.T0, acc[0][lane], acc[1][lane], nb, Tb);
+  const double gb = Gb_all + acc[2][lane], ub = Ub_all + acc[3][lane];
   double mu[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   landau_adjoint(m, M, 0.0, 0.0, gb, ub, nb, Tb, mu);
   double* cb = a.cellbuf + 7 * tb.cell_off;
@@ -84,7 +132,7 @@ __global__ __launch_bounds__(256) void adj_reduce_kernel(AdjArgs<Real> a) {
   cb[5 * ldx + y] = double(g0);
   cb[6 * ldx + y] = double(g1);
   double* ta = a.tau_acc + tb.cell_off;
-  ta[y] = (a.tau_init ? 0.0 : ta[y]) + a.cJ * taup;
+  ta[y] = (a.tau_init ? 0.0 : ta[y]) + a.cJ * taup_all;
 }
 
 template <typename Real>
@@ -273,7 +321,8 @@ __global__ void init_adjoint_final_kernel(const TubeDev* tubes, int tube, const 
 
 template <typename Real, int QPT, int NVT>
 hipError_t adjoint_stage_t(int nx, int Q, const AdjArgs<Real>& a, hipStream_t s) {
-  hipLaunchKernelGGL((adj_reduce_kernel<Real, QPT, NVT>), dim3((nx + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((adj_reduce_kernel<Real, QPT, NVT>), dim3((nx + kRedCells - 1) / kRedCells),
+                     dim3(kRedCells * kRedGroups), 0, s, a);
   hipLaunchKernelGGL(adj_faces_kernel<Real>, dim3((nx + 1 + 255) / 256, Q), dim3(256), 0, s, a);
   hipLaunchKernelGGL(adj_combine_kernel<Real>, dim3((nx + 255) / 256, Q), dim3(256), 0, s, a);
   return hipGetLastError();

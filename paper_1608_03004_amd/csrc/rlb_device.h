@@ -93,16 +93,18 @@ __device__ inline Macro landau(const double m[5]) {
 // which is the orthogonal projection of eq. feqtrunc (the Laplace transform of
 // the Laguerre polynomials done in closed form, the xi integral by a symmetric
 // auxiliary Gauss-Legendre rule whose node pairs +-xi_a share one pass).
+// Raw sums of the projection over the auxiliary node pairs a = a_first,
+// a_first + a_step, ... (all pairs: 0, 1), before the prefactor.
 template <typename Real, int QPT, int NVT>
-__device__ inline void feq_coefficients(Real n, Real T, Real gamma, Real u, Real T0, int qp, int np, int nv,
-                                        cptr<double> itab, cptr<Real> aux,
-                                        int aux_pairs, Real D[QPT][NVT + 1]) {
+__device__ inline void feq_projection_sums(Real T, Real gamma, Real u, Real T0, int qp, int np, cptr<double> itab,
+                                           cptr<Real> aux, int aux_pairs, int a_first, int a_step,
+                                           Real D[QPT][NVT + 1]) {
 #pragma unroll
   for (int i = 0; i < QPT; ++i)
 #pragma unroll
     for (int k = 0; k <= NVT; ++k) D[i][k] = Real(0);
   const Real r = T / T0;
-  for (int a = 0; a < aux_pairs; ++a) {
+  for (int a = a_first; a < aux_pairs; a += a_step) {
     cptr<Real> A = aux + a * kAuxStride;
     const Real xa = A[0];
     const Real yp = fast_div(Real(1), gamma - xa * u);
@@ -125,11 +127,24 @@ __device__ inline void feq_coefficients(Real n, Real T, Real gamma, Real u, Real
       }
     }
   }
+}
+
+// Prefactor n / (4 T T0^2) and truncation at n_v applied to the raw sums.
+template <typename Real, int QPT, int NVT>
+__device__ inline void feq_scale(Real n, Real T, Real T0, int nv, Real D[QPT][NVT + 1]) {
   const Real pref = n / (Real(4) * T * T0 * T0);
 #pragma unroll
   for (int i = 0; i < QPT; ++i)
 #pragma unroll
     for (int k = 0; k <= NVT; ++k) D[i][k] = (k <= nv) ? D[i][k] * pref : Real(0);
+}
+
+template <typename Real, int QPT, int NVT>
+__device__ inline void feq_coefficients(Real n, Real T, Real gamma, Real u, Real T0, int qp, int np, int nv,
+                                        cptr<double> itab, cptr<Real> aux,
+                                        int aux_pairs, Real D[QPT][NVT + 1]) {
+  feq_projection_sums<Real, QPT, NVT>(T, gamma, u, T0, qp, np, itab, aux, aux_pairs, 0, 1, D);
+  feq_scale<Real, QPT, NVT>(n, T, T0, nv, D);
 }
 
 // Fifth-order WENO (Jiang-Shu) value at the face between v3 and v4 from the
@@ -213,15 +228,17 @@ __device__ inline void landau_adjoint(const double m[5], const Macro& M, double 
 
 // Adjoint of feq_coefficients (evaluated in FP64 on the same auxiliary rule):
 // given Db[i][k] = dL/dD[i][k], accumulates dL/d(n, T, gamma, u).
+// Reverse sweep of the projection over the auxiliary pairs a = a_first,
+// a_first + a_step, ...: accumulates the adjoints of the prefactor (prefb),
+// of r = T/T0 (rb), of gamma (gb) and of u (ub).
 template <int QPT, int NVT>
-__device__ inline void feq_coefficients_adjoint(double n, double T, double gamma, double u, double T0, int qp, int np,
-                                                int nv, cptr<double> itab, cptr<double> aux, int aux_pairs,
-                                                const double Db[QPT][NVT + 1], double& nb, double& Tb, double& gb,
-                                                double& ub) {
+__device__ inline void feq_adjoint_sums(double n, double T, double gamma, double u, double T0, int qp, int np, int nv,
+                                        cptr<double> itab, cptr<double> aux, int aux_pairs, int a_first, int a_step,
+                                        const double Db[QPT][NVT + 1], double& prefb, double& rb, double& gb,
+                                        double& ub) {
   const double pref = n / (4.0 * T * T0 * T0);
   const double r = T / T0;
-  double prefb = 0.0, rb = 0.0;
-  for (int a = 0; a < aux_pairs; ++a) {
+  for (int a = a_first; a < aux_pairs; a += a_step) {
     cptr<double> A = aux + a * kAuxStride;
     const double xa = A[0];
     const double yp = 1.0 / (gamma - xa * u), ym = 1.0 / (gamma + xa * u);
@@ -262,8 +279,24 @@ __device__ inline void feq_coefficients_adjoint(double n, double T, double gamma
     gb -= ypb * yp2 + ymb * ym2;
     ub += ypb * xa * yp2 - ymb * xa * ym2;
   }
+}
+
+// Adjoint of the prefactor: prefb, rb -> n and T.
+__device__ inline void feq_adjoint_finish(double n, double T, double T0, double prefb, double rb, double& nb,
+                                          double& Tb) {
+  const double pref = n / (4.0 * T * T0 * T0);
   nb += prefb * pref / n;
   Tb += -prefb * pref / T + rb / T0;
+}
+
+template <int QPT, int NVT>
+__device__ inline void feq_coefficients_adjoint(double n, double T, double gamma, double u, double T0, int qp, int np,
+                                                int nv, cptr<double> itab, cptr<double> aux, int aux_pairs,
+                                                const double Db[QPT][NVT + 1], double& nb, double& Tb, double& gb,
+                                                double& ub) {
+  double prefb = 0.0, rb = 0.0;
+  feq_adjoint_sums<QPT, NVT>(n, T, gamma, u, T0, qp, np, nv, itab, aux, aux_pairs, 0, 1, Db, prefb, rb, gb, ub);
+  feq_adjoint_finish(n, T, T0, prefb, rb, nb, Tb);
 }
 
 // Gradient of the WENO5 value with respect to its five upwind-ordered inputs.
