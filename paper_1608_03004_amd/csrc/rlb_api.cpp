@@ -26,8 +26,13 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 struct Group {
   int qpt, nvt;
+  int qp_max;                // largest q_p of the group's tubes
   int item_begin, item_end;  // range in the item list
 };
+
+// Lattices up to this many cells keep a per-node sum buffer, so that stages
+// of small problems can spread the radial nodes over workgroups.
+constexpr int64_t kSplitMaxCells = int64_t(1) << 18;
 
 }  // namespace
 
@@ -51,6 +56,8 @@ struct rlb_lattice {
   size_t off_F[3] = {0, 0, 0}, off_rec[3] = {0, 0, 0};
   size_t off_tubes = 0, off_jtab = 0, off_itab = 0, off_aux = 0, off_aux_d = 0, off_items = 0, off_sides = 0,
          off_mask = 0, off_flag = 0, off_fields = 0, off_totals = 0, total = 0;
+  size_t off_part = 0;  // per-node sums of split launches (0: none)
+  int part_stride = 0;  // doubles per cell in that buffer
   // adjoint workspace (RLB_WITH_ADJOINT)
   int64_t cell_elems = 0, face_elems = 0;
   int init_blocks_max = 0;
@@ -164,8 +171,10 @@ void build_items(rlb_lattice* L) {
     g.qpt = kv.first.first;
     g.nvt = kv.first.second;
     g.item_begin = static_cast<int>(L->items.size());
+    g.qp_max = 1;
     std::vector<std::pair<int64_t, WorkItem>> tmp;
     for (int t : kv.second) {
+      g.qp_max = std::max(g.qp_max, L->desc[t].q_p);
       const int64_t cost = int64_t(L->desc[t].q_xi) * L->desc[t].q_p;
       for (int x0 = 0; x0 < L->desc[t].nx; x0 += tile) tmp.push_back({cost, WorkItem{t, x0}});
     }
@@ -197,55 +206,57 @@ LaunchShape shape(const rlb_lattice* L, const Group& g) {
   ls.tile = L->sched.tile;
   const int n = g.item_end - g.item_begin;
   ls.grid = n;
+  ls.nodes = 1;
   if (L->sched.persistent) ls.grid = std::max(1, std::min(n, L->sched.blocks_per_cu * std::max(1, L->cu_count)));
+  // too few tiles to fill the GPU: one workgroup per (tile, radial node)
+  else if (L->off_part && g.qp_max > 1 && n < L->cu_count) ls.nodes = g.qp_max;
   return ls;
+}
+
+// One SSP-RK3 stage of one kernel group with explicit buffers: the stage
+// kernel and, for a split launch, the kernel that forms the records.
+template <typename Real>
+hipError_t stage_group(rlb_lattice* L, const Group& g, int stage, const void* fin, const void* fn, void* fout,
+                       const double* rec_in, double* rec_out, hipStream_t s) {
+  const LaunchShape ls = shape(L, g);
+  StageArgs<Real> a;
+  a.tubes = L->dev<TubeDev>(L->off_tubes);
+  a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
+  a.nitems = g.item_end - g.item_begin;
+  a.stage = stage;
+  a.aux_pairs = L->aux_pairs;
+  a.jtab = L->dev<Real>(L->off_jtab);
+  a.itab = L->dev<double>(L->off_itab);
+  a.aux = L->dev<Real>(L->off_aux);
+  a.fin = static_cast<const Real*>(fin);
+  a.fn = static_cast<const Real*>(fn);
+  a.fout = static_cast<Real*>(fout);
+  a.rec_in = rec_in;
+  a.rec_out = rec_out;
+  a.flag = L->dev<unsigned>(L->off_flag);
+  a.part = ls.nodes > 1 ? L->dev<double>(L->off_part) : nullptr;
+  a.part_stride = L->part_stride;
+  hipError_t e = launch_stage(sizeof(Real) == 4, g.qpt, g.nvt, ls, &a, s);
+  if (e == hipSuccess && ls.nodes > 1)
+    e = launch_combine(a.tubes, a.items, a.nitems, ls.tile, a.itab, a.part, a.part_stride, rec_out, s);
+  return e;
 }
 
 rlb_status enqueue_steps(rlb_lattice* L, hipStream_t s, int64_t nsteps) {
   const bool fp32 = L->prec == RLB_FP32;
   for (int64_t n = 0; n < nsteps; ++n) {
     for (int stage = 1; stage <= 3; ++stage) {
+      const int fin = stage == 1 ? 0 : (stage == 2 ? 1 : 2);
+      const int fout = stage == 1 ? 1 : (stage == 2 ? 2 : 0);
+      const int rin = fin, rout = fout;
       for (const Group& g : L->groups) {
-        const LaunchShape ls = shape(L, g);
-        const int fin = stage == 1 ? 0 : (stage == 2 ? 1 : 2);
-        const int fout = stage == 1 ? 1 : (stage == 2 ? 2 : 0);
-        const int rin = fin, rout = fout;
-        hipError_t e;
-        if (fp32) {
-          StageArgs<float> a;
-          a.tubes = L->dev<TubeDev>(L->off_tubes);
-          a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
-          a.nitems = g.item_end - g.item_begin;
-          a.stage = stage;
-          a.aux_pairs = L->aux_pairs;
-          a.jtab = L->dev<float>(L->off_jtab);
-          a.itab = L->dev<double>(L->off_itab);
-          a.aux = L->dev<float>(L->off_aux);
-          a.fin = L->dev<float>(L->off_F[fin]);
-          a.fn = L->dev<float>(L->off_F[0]);
-          a.fout = L->dev<float>(L->off_F[fout]);
-          a.rec_in = L->dev<double>(L->off_rec[rin]);
-          a.rec_out = L->dev<double>(L->off_rec[rout]);
-          a.flag = L->dev<unsigned>(L->off_flag);
-          e = launch_stage(1, g.qpt, g.nvt, ls, &a, s);
-        } else {
-          StageArgs<double> a;
-          a.tubes = L->dev<TubeDev>(L->off_tubes);
-          a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
-          a.nitems = g.item_end - g.item_begin;
-          a.stage = stage;
-          a.aux_pairs = L->aux_pairs;
-          a.jtab = L->dev<double>(L->off_jtab);
-          a.itab = L->dev<double>(L->off_itab);
-          a.aux = L->dev<double>(L->off_aux);
-          a.fin = L->dev<double>(L->off_F[fin]);
-          a.fn = L->dev<double>(L->off_F[0]);
-          a.fout = L->dev<double>(L->off_F[fout]);
-          a.rec_in = L->dev<double>(L->off_rec[rin]);
-          a.rec_out = L->dev<double>(L->off_rec[rout]);
-          a.flag = L->dev<unsigned>(L->off_flag);
-          e = launch_stage(0, g.qpt, g.nvt, ls, &a, s);
-        }
+        const void* Fin = L->ws + L->off_F[fin];
+        const void* Fn = L->ws + L->off_F[0];
+        void* Fout = L->ws + L->off_F[fout];
+        const double* Rin = L->dev<double>(L->off_rec[rin]);
+        double* Rout = L->dev<double>(L->off_rec[rout]);
+        const hipError_t e = fp32 ? stage_group<float>(L, g, stage, Fin, Fn, Fout, Rin, Rout, s)
+                                  : stage_group<double>(L, g, stage, Fin, Fn, Fout, Rin, Rout, s);
         if (e != hipSuccess) return hip_fail(L, e, "stage kernel launch");
       }
     }
@@ -468,6 +479,12 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
   L->off_flag = o; o = align256(o + 16);
   L->off_fields = o; o = align256(o + 10 * size_t(L->max_ldx) * 8);
   L->off_totals = o; o = align256(o + 4 * 8);
+  if (L->cell_elems <= kSplitMaxCells) {
+    int qp_max = 1;
+    for (auto& d : L->desc) qp_max = std::max(qp_max, d.q_p);
+    L->part_stride = 3 * qp_max;
+    L->off_part = o; o = align256(o + size_t(L->cell_elems) * L->part_stride * 8);
+  }
   if (flags & RLB_WITH_ADJOINT) {
     for (int k = 0; k < 2; ++k) { L->off_aF[k] = o; o = align256(o + L->state_elems * L->rsize); }
     for (int k = 0; k < 3; ++k) { L->off_arec[k] = o; o = align256(o + L->rec_elems * 8); }
@@ -791,43 +808,8 @@ rlb_status run_stage(rlb_lattice* L, int stage, const void* fin, const void* fn,
                      double* rec_out) {
   const bool fp32 = L->prec == RLB_FP32;
   for (const Group& g : L->groups) {
-    const LaunchShape ls = shape(L, g);
-    hipError_t e;
-    if (fp32) {
-      StageArgs<float> a;
-      a.tubes = L->dev<TubeDev>(L->off_tubes);
-      a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
-      a.nitems = g.item_end - g.item_begin;
-      a.stage = stage;
-      a.aux_pairs = L->aux_pairs;
-      a.jtab = L->dev<float>(L->off_jtab);
-      a.itab = L->dev<double>(L->off_itab);
-      a.aux = L->dev<float>(L->off_aux);
-      a.fin = static_cast<const float*>(fin);
-      a.fn = static_cast<const float*>(fn);
-      a.fout = static_cast<float*>(fout);
-      a.rec_in = rec_in;
-      a.rec_out = rec_out;
-      a.flag = L->dev<unsigned>(L->off_flag);
-      e = launch_stage(1, g.qpt, g.nvt, ls, &a, L->stream);
-    } else {
-      StageArgs<double> a;
-      a.tubes = L->dev<TubeDev>(L->off_tubes);
-      a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
-      a.nitems = g.item_end - g.item_begin;
-      a.stage = stage;
-      a.aux_pairs = L->aux_pairs;
-      a.jtab = L->dev<double>(L->off_jtab);
-      a.itab = L->dev<double>(L->off_itab);
-      a.aux = L->dev<double>(L->off_aux);
-      a.fin = static_cast<const double*>(fin);
-      a.fn = static_cast<const double*>(fn);
-      a.fout = static_cast<double*>(fout);
-      a.rec_in = rec_in;
-      a.rec_out = rec_out;
-      a.flag = L->dev<unsigned>(L->off_flag);
-      e = launch_stage(0, g.qpt, g.nvt, ls, &a, L->stream);
-    }
+    const hipError_t e = fp32 ? stage_group<float>(L, g, stage, fin, fn, fout, rec_in, rec_out, L->stream)
+                              : stage_group<double>(L, g, stage, fin, fn, fout, rec_in, rec_out, L->stream);
     if (e != hipSuccess) return hip_fail(L, e, "stage kernel launch");
   }
   return RLB_OK;

@@ -89,6 +89,12 @@ struct StageArgs {
   const double* rec_in;
   double* rec_out;
   unsigned* flag;
+  // split launch (grid.y = radial node): each block writes its node's three
+  // plain sums per cell to part[(cell_off + x) * part_stride + 3 i + c] and
+  // combine_kernel forms the records; nullptr: one block per item, records
+  // written by the stage kernel
+  double* part;
+  int32_t part_stride;
 };
 
 template <typename Real>
@@ -111,6 +117,7 @@ struct InitArgs {
 struct LaunchShape {
   int tile;
   int grid;
+  int nodes;  // 1, or the group's radial-node bound for a split launch
 };
 hipError_t launch_stage(int prec_fp32, int qpt, int nvt, const LaunchShape& ls, const void* args,
                         hipStream_t stream);
@@ -122,6 +129,8 @@ hipError_t launch_fields(const TubeDev* tubes, int tube, int nx, const double* r
                          unsigned* flag, hipStream_t stream);
 hipError_t launch_totals(const TubeDev* tubes, int tube, const double* rec, double* out, hipStream_t stream);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+hipError_t launch_combine(const TubeDev* tubes, const WorkItem* items, int nitems, int tile, const double* itab,
+                          const double* part, int part_stride, double* rec_out, hipStream_t stream);
 
 // Adjoint launchers (defined in rlb_adjoint.hip); one tube per call.
 hipError_t launch_adjoint_stage(int prec_fp32, int qpt, int nvt, int nx, int Q, const void* args, hipStream_t stream);

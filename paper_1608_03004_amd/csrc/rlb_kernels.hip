@@ -71,6 +71,20 @@ __device__ inline void row_moments(const Real* jtab, int qx, Get get, double& s0
   s2 = a2.value();
 }
 
+// Adds one radial node's plain sums s0 = sum w F, s1 = sum w xi F,
+// s2 = sum w xi^2 F (quadrature weights of the polar rule) to the five
+// moment records N0, Nz, T00, T0z, Tzz of a cell.  Every kernel that forms
+// records goes through it, node by node in order, so that records of the
+// same state agree to the bit.
+template <typename Ptr>
+__device__ inline void add_node(double m[5], Ptr I, double s0, double s1, double s2) {
+  m[0] = fma(I[2], s0, m[0]);
+  m[1] = fma(I[2], s1, m[1]);
+  m[2] = fma(I[3], s0, m[2]);
+  m[3] = fma(I[3], s1, m[3]);
+  m[4] = fma(I[3], s2, m[4]);
+}
+
 // LDS layout of a chunk: value (c, p) -- chunk point c, tile position p --
 // at plane[c / V][p][c % V], V = 16 / sizeof(Real), so that one lane's values
 // of V consecutive chunk points are one 16-byte word and consecutive lanes
@@ -241,9 +255,16 @@ __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
     const cptr<Real> jtab = as_const(a.jtab) + int64_t(tbp->jrow) * kJStride;
     const cptr<double> itab = as_const(a.itab) + int64_t(tbp->irow) * kIStride;
 
+    // radial nodes of this block: all of them, or node blockIdx.y of a split
+    // launch (whose blocks beyond the tube's q_p have nothing to do)
+    const bool split = a.part != nullptr;
+    const int i_first = split ? int(blockIdx.y) : 0;
+    if (i_first >= qp) continue;
+    const int i_last = split ? i_first + 1 : qp;
+
     // first chunk's loads go out before the per-cell prologue
     ChunkLoads<Real, CH> bufA, bufB;
-    issue_chunk<Real, TILE, CH>(fin, ldx, row_bytes, qx, 0, 0, vx, t, x0, nx, bufA);
+    issue_chunk<Real, TILE, CH>(fin, ldx, row_bytes, qx, i_first, 0, vx, t, x0, nx, bufA);
 
     // 1-2. moments of the stage input -> Landau frame (FP64)
     double m[5];
@@ -281,7 +302,7 @@ __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
          // very last chunk re-loads itself
         int in = i, jn = j0 + CH;
         if (jn >= qx) { in = i + 1; jn = 0; }
-        if (in >= qp) { in = i; jn = j0; }
+        if (in >= i_last) { in = i; jn = j0; }
         issue_chunk<Real, TILE, CH>(fin, ldx, row_bytes, qx, in, jn, vx, t, x0, nx, nxt);
       }
 #pragma unroll
@@ -396,11 +417,12 @@ __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
     // the scarce resource here); each lane only touches its own column
 #pragma unroll
     for (int c = 0; c < 5; ++c) mom[c][t] = 0.0;
+    double* part = split ? a.part + (tbp->cell_off + xc) * a.part_stride : nullptr;
     // runtime loop over radial nodes (the node's coefficient row is selected
     // with uniform conditional moves); the chunk loop alternates the two
     // register buffers so that no in-flight load is ever copied
 #pragma unroll 1
-    for (int i = 0; i < qp; ++i) {
+    for (int i = i_first; i < i_last; ++i) {
       Real Dc[NVT + 1];
 #pragma unroll
       for (int k = 0; k <= NVT; ++k) {
@@ -417,15 +439,23 @@ __global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
         else
           bufA = bufB;  // odd number of chunks per node: the next node starts in A
       }
-      const cptr<double> I = itab + i * kIStride;
       const double s0 = acc.a0.value(), s1 = acc.a1.value(), s2 = acc.a2.value();
-      mom[0][t] += I[2] * s0;
-      mom[1][t] += I[2] * s1;
-      mom[2][t] += I[3] * s0;
-      mom[3][t] += I[3] * s1;
-      mom[4][t] += I[3] * s2;
+      if (split) {
+        if (valid) {
+          part[3 * i] = s0;
+          part[3 * i + 1] = s1;
+          part[3 * i + 2] = s2;
+        }
+      } else {
+        double m5[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) m5[c] = mom[c][t];
+        add_node(m5, itab + i * kIStride, s0, s1, s2);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) mom[c][t] = m5[c];
+      }
     }
-    if (valid) {
+    if (valid && !split) {
       double* ro = a.rec_out + tbp->rec_off;
 #pragma unroll
       for (int c = 0; c < 5; ++c) ro[c * ldx + x] = mom[c][t];
@@ -470,11 +500,7 @@ __global__ __launch_bounds__(TILE) void init_kernel(InitArgs<Real> a) {
         double s0, s1, s2;
         row_moments<Real>(jtab, tb.qx, [&](int j) { return row[int64_t(j) * tb.ldx]; }, s0, s1, s2);
         const double* I = itab + i * kIStride;
-        mom[0] += I[2] * s0;
-        mom[1] += I[2] * s1;
-        mom[2] += I[3] * s0;
-        mom[3] += I[3] * s1;
-        mom[4] += I[3] * s2;
+        add_node(mom, I, s0, s1, s2);
       }
     }
     double* rec = a.rec + tb.rec_off;
@@ -503,11 +529,7 @@ __global__ __launch_bounds__(256) void moments_kernel(const TubeDev* tubes, cons
         double s0, s1, s2;
         row_moments<Real>(jtab, tb.qx, [&](int j) { return row[int64_t(j) * tb.ldx]; }, s0, s1, s2);
         const double* I = itab + i * kIStride;
-        mom[0] += I[2] * s0;
-        mom[1] += I[2] * s1;
-        mom[2] += I[3] * s0;
-        mom[3] += I[3] * s1;
-        mom[4] += I[3] * s2;
+        add_node(mom, I, s0, s1, s2);
       }
       double* rec = rec_all + tb.rec_off;
       for (int c = 0; c < 5; ++c) rec[int64_t(c) * tb.ldx + x] = mom[c];
@@ -557,6 +579,28 @@ __global__ __launch_bounds__(256) void totals_kernel(const TubeDev* tubes, int t
     for (int c = 0; c < 3; ++c) out[c] = red[c][0] * tb.dz;
 }
 
+// Records of a split stage launch: the five moments of each cell from the
+// per-node sums, in node order (the same operations as the unsplit kernel).
+__global__ __launch_bounds__(256) void combine_kernel(const TubeDev* tubes, const WorkItem* items, int nitems,
+                                                      int tile, const double* itab_all, const double* part,
+                                                      int part_stride, double* rec_all) {
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const WorkItem wi = items[item];
+    const TubeDev& tb = tubes[wi.tube];
+    for (int t = threadIdx.x; t < tile; t += blockDim.x) {
+      const int x = wi.x0 + t;
+      if (x >= tb.nx) continue;
+      const double* itab = itab_all + int64_t(tb.irow) * kIStride;
+      const double* p = part + (tb.cell_off + x) * part_stride;
+      double mom[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+      for (int i = 0; i < tb.qp; ++i) add_node(mom, itab + i * kIStride, p[3 * i], p[3 * i + 1], p[3 * i + 2]);
+      double* rec = rec_all + tb.rec_off;
+#pragma unroll
+      for (int c = 0; c < 5; ++c) rec[int64_t(c) * tb.ldx + x] = mom[c];
+    }
+  }
+}
+
 // Plain streaming copy (16-byte vectors), for bandwidth calibration.
 __global__ __launch_bounds__(256) void copy_kernel(uint4* __restrict__ dst, const uint4* __restrict__ src,
                                                    size_t n16) {
@@ -568,10 +612,11 @@ template <typename Real, int TILE, int QPT, int NVT>
 hipError_t launch_stage_t(const LaunchShape& ls, const void* args, hipStream_t s) {
   const StageArgs<Real>& a = *static_cast<const StageArgs<Real>*>(args);
   constexpr int CH = chunk_points<Real>();
+  const dim3 grid(ls.grid, ls.nodes);
   if (a.stage == 1)
-    hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, false, CH>), dim3(ls.grid), dim3(TILE), 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, false, CH>), grid, dim3(TILE), 0, s, a);
   else
-    hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, true, CH>), dim3(ls.grid), dim3(TILE), 0, s, a);
+    hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, true, CH>), grid, dim3(TILE), 0, s, a);
   return hipGetLastError();
 }
 
@@ -646,6 +691,13 @@ hipError_t launch_fields(const TubeDev* tubes, int tube, int nx, const double* r
 
 hipError_t launch_totals(const TubeDev* tubes, int tube, const double* rec, double* out, hipStream_t stream) {
   hipLaunchKernelGGL(totals_kernel, dim3(1), dim3(256), 0, stream, tubes, tube, rec, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const TubeDev* tubes, const WorkItem* items, int nitems, int tile, const double* itab,
+                          const double* part, int part_stride, double* rec_out, hipStream_t stream) {
+  hipLaunchKernelGGL(combine_kernel, dim3(nitems), dim3(256), 0, stream, tubes, items, nitems, tile, itab, part,
+                     part_stride, rec_out);
   return hipGetLastError();
 }
 
