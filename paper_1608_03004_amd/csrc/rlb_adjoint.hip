@@ -66,12 +66,27 @@ __global__ __launch_bounds__(kRedCells * kRedGroups) void adj_reduce_kernel(AdjA
   for (int c = 0; c < 5; ++c) m[c] = a.rec_g[tb.rec_off + c * ldx + yc];
   const Macro M = landau(m);
 
-  // 1. projection coefficients, evaluated exactly as the forward stage kernel
-  //    does (every group; f - f^eq is small, so the reduction below needs the
-  //    forward's f^eq to the last bit)
+  // 1. projection coefficients, bit for bit those of the forward stage kernel
+  //    (f - f^eq is small, so the reduction below needs the forward's f^eq
+  //    exactly): group grp sums the rows of radial nodes grp, grp + G, ...
+  //    over all pairs in the forward's order, and the rows are exchanged
   Real D[QPT][NVT + 1];
-  feq_coefficients<Real, QPT, NVT>(Real(M.n), Real(M.T), Real(M.gamma), Real(M.u), Real(tb.T0), qp, tb.np, tb.nv,
-                                   itab, as_const(a.aux), a.aux_pairs, D);
+  {
+    feq_projection_sums<Real, QPT, NVT>(Real(M.T), Real(M.gamma), Real(M.u), Real(tb.T0), qp, tb.np, itab,
+                                        as_const(a.aux), a.aux_pairs, 0, 1, D, grp, kRedGroups);
+#pragma unroll
+    for (int i = 0; i < QPT; ++i)
+      if (i % kRedGroups == grp)
+#pragma unroll
+        for (int k = 0; k <= NVT; ++k) acc[i * (NVT + 1) + k][lane] = double(D[i][k]);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < QPT; ++i)
+#pragma unroll
+      for (int k = 0; k <= NVT; ++k) D[i][k] = Real(acc[i * (NVT + 1) + k][lane]);
+    feq_scale<Real, QPT, NVT>(Real(M.n), Real(M.T), Real(tb.T0), tb.nv, D);
+    __syncthreads();  // acc is reused below
+  }
 
   // 2. reduction over the points (group grp takes j = grp, grp + G, ...)
   const double tau_inv = tb.tau_inv;

@@ -94,11 +94,13 @@ __device__ inline Macro landau(const double m[5]) {
 // the Laguerre polynomials done in closed form, the xi integral by a symmetric
 // auxiliary Gauss-Legendre rule whose node pairs +-xi_a share one pass).
 // Raw sums of the projection over the auxiliary node pairs a = a_first,
-// a_first + a_step, ... (all pairs: 0, 1), before the prefactor.
+// a_first + a_step, ... (all pairs: 0, 1), before the prefactor, for the
+// radial nodes i = i_first, i_first + i_step, ... (rows of other nodes are 0).
+// Each row's sum runs over the pairs in the same order for any node subset.
 template <typename Real, int QPT, int NVT>
 __device__ inline void feq_projection_sums(Real T, Real gamma, Real u, Real T0, int qp, int np, cptr<double> itab,
                                            cptr<Real> aux, int aux_pairs, int a_first, int a_step,
-                                           Real D[QPT][NVT + 1]) {
+                                           Real D[QPT][NVT + 1], int i_first = 0, int i_step = 1) {
 #pragma unroll
   for (int i = 0; i < QPT; ++i)
 #pragma unroll
@@ -113,7 +115,7 @@ __device__ inline void feq_projection_sums(Real T, Real gamma, Real u, Real T0, 
     const Real yp2 = yp * yp, ym2 = ym * ym;
 #pragma unroll
     for (int i = 0; i < QPT; ++i) {
-      if (i < qp) {
+      if (i < qp && i >= i_first && (i - i_first) % i_step == 0) {
         cptr<double> L = itab + i * kIStride + 4;
         Real sp = Real(L[np]), sm = Real(L[np]);
         for (int l = np - 1; l >= 0; --l) {
