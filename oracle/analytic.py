@@ -6,7 +6,9 @@
   which every polar node streams exactly.
 * The ideal ultrarelativistic (P = e/3) Riemann problem, the tau -> 0 limit of
   the model: a left rarefaction and a right shock (standard relativistic
-  hydrodynamics, used as the hydrodynamic-regime check of the same section).
+  hydrodynamics, used as the hydrodynamic-regime check of the same section),
+  and the same problem seen from a frame in which both initial states move
+  with a common velocity (moving initial states of eq. condinit).
 
 Everything here is plain numpy/math written from the physics; nothing is
 shared with the GPU path.
@@ -136,3 +138,26 @@ def riemann_profile(z, t, left, right):
         else:
             e[k], v[k], n[k] = eR, 0.0, right[1]
     return e, v, n
+
+
+# ---------------------------------------------------------------------------
+# Boosted frame
+# ---------------------------------------------------------------------------
+def boost_velocity(v, w):
+    """Velocity of a fluid moving at v in a frame that itself moves at w."""
+    return (v + w) / (1.0 + v * w)
+
+
+def riemann_profile_boosted(z, t, left, right, w):
+    """(e, v, n) at z, t > 0 of the Riemann problem whose states, given in their
+    common rest frame as (P, n, 0), both move with velocity w.
+
+    The initial jump sits at z = 0, t = 0 in every frame, so the solution is a
+    function of z/t only: the lab state at s = z/t is the rest-frame state at
+    s' = (s - w)/(1 - s w), with the rest-frame scalars e and n unchanged and
+    the fluid velocity boosted by w.
+    """
+    s = np.asarray(z, dtype=np.float64) / t
+    sp = (s - w) / (1.0 - s * w)
+    e, v, n = riemann_profile(sp, 1.0, left, right)
+    return e, boost_velocity(v, w), n

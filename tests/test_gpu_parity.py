@@ -101,6 +101,22 @@ def test_fp64_moving_states(torch_cuda):
     assert normwise(lat.state_array(0), F).max() < 1e-12
 
 
+@pytest.mark.parametrize("w", [0.3, -0.5])
+def test_fp64_boosted_sod(torch_cuda, w):
+    # Sod states moving together at velocity w (eq. condinit with u_L = u_R);
+    # the oracle's approach to the boosted ideal solution is pinned on the CPU.
+    params = dict(nx=400, q_xi=8, q_p=3, tau=1e-2)
+    u = w / math.sqrt(1 - w * w)
+    left, right = (1.0, 1.0, u), (0.1, 0.125, u)
+    lat = _lattice([params])
+    lat.set_initial_state(left, right)
+    lat.step(40)
+    F, ref = _oracle_run(params, left, right, 40)
+    errs = field_errors(lat.moments(0), ref)
+    assert max(e[0] for e in errs.values()) < 1e-12, errs
+    assert normwise(lat.state_array(0), F).max() < 1e-12
+
+
 def test_fp64_batched_mixed_tubes(torch_cuda):
     plist = [dict(nx=300, q_xi=8, q_p=3, tau=1e-2), dict(nx=64, q_xi=16, q_p=4, tau=1e-1),
              dict(nx=500, q_xi=5, q_p=3, tau=2e-3), dict(nx=130, q_xi=7, q_p=5, n_p=3, n_v=6, tau=1.0)]

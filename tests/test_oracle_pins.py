@@ -377,6 +377,61 @@ def test_riemann_solution_satisfies_jump_conditions():
     assert abs(st["nL"] - (e / 3.0) ** 0.75) < 1e-12
 
 
+def _fluid_flux(e, n, v):
+    """(N0, Nz, T00, T0z, Tzz) of a perfect P = e/3 fluid moving at v."""
+    P, g2 = e / 3.0, 1.0 / (1.0 - v * v)
+    return np.array([n * math.sqrt(g2), n * math.sqrt(g2) * v, (e + P) * g2 - P, (e + P) * g2 * v,
+                     (e + P) * g2 * v * v + P])
+
+
+@pytest.mark.parametrize("w", [0.3, -0.5])
+def test_boosted_riemann_solution_satisfies_lab_frame_jump_conditions(w):
+    # Both Sod states moving at w (eq. condinit with u_L = u_R = gamma_w w): the
+    # boosted solution must conserve N^mu and T^{mu nu} across the shock that
+    # moves at the boosted speed, with every quantity evaluated in the lab frame.
+    st = A.riemann_star(SOD_L, SOD_R)
+    t = 1.0
+    V = A.boost_velocity(st["V"], w)
+    pre = A.riemann_profile_boosted(np.array([V * t + 1e-9]), t, SOD_L, SOD_R, w)
+    post = A.riemann_profile_boosted(np.array([V * t - 1e-9]), t, SOD_L, SOD_R, w)
+    assert abs(pre[1][0] - w) < 1e-15 and abs(post[1][0] - A.boost_velocity(st["v"], w)) < 1e-15
+    a = _fluid_flux(pre[0][0], pre[2][0], pre[1][0])
+    b = _fluid_flux(post[0][0], post[2][0], post[1][0])
+    # [flux] = V [density] for N^mu, T^{0 mu} and T^{z mu}
+    assert abs((b[1] - a[1]) - V * (b[0] - a[0])) < 1e-12
+    assert abs((b[3] - a[3]) - V * (b[2] - a[2])) < 1e-12
+    assert abs((b[4] - a[4]) - V * (b[3] - a[3])) < 1e-12
+    # w = 0 is the rest-frame solution
+    z = np.linspace(-0.5, 0.5, 41)
+    for x, y in zip(A.riemann_profile_boosted(z, 0.2, SOD_L, SOD_R, 0.0), A.riemann_profile(z, 0.2, SOD_L, SOD_R)):
+        assert np.array_equal(x, y)
+
+
+def test_boosted_sod_approaches_boosted_ideal_solution():
+    # Moving initial states: the oracle's profile approaches the boosted ideal
+    # solution as tau decreases, as closely as the rest-frame one does.
+    w = 0.3
+    u = w / math.sqrt(1 - w * w)
+    left, right = (SOD_L[0], SOD_L[1], u), (SOD_R[0], SOD_R[1], u)
+    t_end = 0.2
+    errs, rest = [], None
+    for tau in (1e-2, 1e-3):
+        tube = O.Tube(nx=800, q_xi=8, q_p=3, tau=tau)
+        nsteps = int(round(t_end / tube.step_dt))
+        t = nsteps * tube.step_dt
+        f = O.fields(tube, O.run(tube, left, right, nsteps))
+        e, v, n = A.riemann_profile_boosted(tube.z(), t, SOD_L, SOD_R, w)
+        errs.append(np.abs(f[5] - e).sum() * tube.dz)
+        if tau == 1e-3:
+            fr = O.fields(tube, O.run(tube, SOD_L, SOD_R, nsteps))
+            er, _, _ = A.riemann_profile(tube.z(), t, SOD_L, SOD_R)
+            rest = np.abs(fr[5] - er).sum() * tube.dz
+            # the velocity field is the boosted one too
+            assert np.abs(f[7] - v).sum() * tube.dz < 0.005
+    assert errs[1] < 0.6 * errs[0], errs
+    assert errs[1] < 1.5 * rest, (errs, rest)
+
+
 def test_hydrodynamic_limit_approaches_ideal_riemann_solution():
     # Viscosity scales with tau, so the profile approaches the ideal P = e/3
     # solution as tau decreases (section Numerical results, hydrodynamic regime).
