@@ -129,8 +129,9 @@ rlb_status rlb_destroy(rlb_lattice* lat);
 
 /* Bytes of device workspace the lattice needs (256-byte aligned base). */
 rlb_status rlb_workspace_size(const rlb_lattice* lat, size_t* bytes);
-/* Attaches caller-owned device memory and the stream; uploads the tables
- * (queued on the stream).  May be called again to move the lattice. */
+/* Attaches caller-owned device memory and the stream, clears it and uploads
+ * the tables (synchronizes the stream).  May be called again to move the
+ * lattice; the state must then be set again. */
 rlb_status rlb_bind(rlb_lattice* lat, void* workspace, size_t bytes, void* hip_stream);
 rlb_status rlb_set_stream(rlb_lattice* lat, void* hip_stream);
 rlb_status rlb_set_schedule(rlb_lattice* lat, const rlb_schedule* sched);
@@ -188,6 +189,16 @@ rlb_status rlb_tables(const rlb_lattice* lat, int32_t tube, double* xi, double* 
  *   intermediate stages are recomputed from state_n.  dL_dtau[t] (device, one
  *   double per tube) is incremented by the step's contribution to dL/dtau_t at
  *   fixed time step.  state_n and lambda must not overlap.
+ * rlb_adjoint_segment: the reverse sweep over one checkpoint segment of
+ *   nsteps >= 1 steps starting from state0 = f^n (the sqrt(N) checkpointing of
+ *   the adjoint): recomputes the segment's states f^{n+k} and their stage
+ *   states f1, f2 into `scratch` (device, caller-owned, at least
+ *   rlb_adjoint_segment_size bytes), then applies the adjoint step to each
+ *   step in reverse order, so lambda goes from dL/df^{n+nsteps} to dL/df^n
+ *   and dL_dtau accumulates.  The result equals, bit for bit, nsteps calls of
+ *   rlb_adjoint_step on the same states; the stage states are computed once
+ *   instead of twice.  The lattice's own state is not touched.  state0,
+ *   scratch and lambda must not overlap.
  * rlb_fields_adjoint: writes into tube's rows of lambda the gradient dL/df of a
  *   loss on the fields of `state` (the rows of rlb_fields: N0, Nz, T00, T0z,
  *   Tzz, e, n, v, T, |N|), given dL_dfields [10][ld] (device, FP64).
@@ -195,6 +206,9 @@ rlb_status rlb_tables(const rlb_lattice* lat, int32_t tube, double* xi, double* 
  *   dL/d(P, n, u) of the left and right states of eq. condinit; synchronizes.
  */
 rlb_status rlb_adjoint_step(rlb_lattice* lat, const void* state_n, void* lambda, double* dL_dtau);
+rlb_status rlb_adjoint_segment_size(const rlb_lattice* lat, int32_t nsteps, size_t* bytes);
+rlb_status rlb_adjoint_segment(rlb_lattice* lat, const void* state0, int32_t nsteps, void* scratch, size_t bytes,
+                               void* lambda, double* dL_dtau);
 rlb_status rlb_fields_adjoint(rlb_lattice* lat, int32_t tube, const void* state, const double* dL_dfields, int64_t ld,
                               void* lambda);
 rlb_status rlb_initial_state_adjoint(rlb_lattice* lat, int32_t tube, const void* lambda0, double grad_left[3],

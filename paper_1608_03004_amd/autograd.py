@@ -4,9 +4,10 @@ hand-written discrete adjoint.
 
 Memory is bounded by checkpointing: the forward keeps every c-th state
 (c = ceil(sqrt(nsteps)) by default); the backward walks the segments in
-reverse, recomputes each segment's states from its checkpoint and applies
-rlb_adjoint_step to them in reverse order.  The time step is held fixed:
-the gradient with respect to tau is taken at constant dt.
+reverse and hands each checkpoint to rlb_adjoint_segment, which recomputes
+the segment's states (with their stage states, kept in one scratch buffer of
+c steps) and applies the adjoint of every step in reverse order.  The time
+step is held fixed: the gradient with respect to tau is taken at constant dt.
 """
 import math
 
@@ -51,17 +52,11 @@ class SodProfile(torch.autograd.Function):
         lat.fields_adjoint(0, ctx.final, dfields, lam)
         dtau = torch.zeros(len(lat.tubes), dtype=torch.float64, device=lat.device)
         bounds = [k for k, _ in ctx.checkpoints] + [ctx.nsteps]
+        longest = max(k1 - k0 for (k0, _), k1 in zip(ctx.checkpoints, bounds[1:]))
+        scratch = torch.empty(lat.adjoint_segment_size(longest), dtype=torch.uint8, device=lat.device)
         for seg in range(len(ctx.checkpoints) - 1, -1, -1):
             k0, state = ctx.checkpoints[seg]
-            k1 = bounds[seg + 1]
-            states = [state]
-            if k1 - k0 > 1:
-                lat.set_state(state)
-                for _ in range(k0 + 1, k1):
-                    lat.step(1)
-                    states.append(lat.get_state().clone())
-            for F in reversed(states):
-                lat.adjoint_step(F, lam, dtau)
+            lat.adjoint_segment(state, bounds[seg + 1] - k0, scratch, lam, dtau)
         gl, gr = lat.initial_state_adjoint(0, lam)
         dev, f64 = lat.device, torch.float64
         g = lambda v: torch.tensor(v, dtype=f64, device=dev)

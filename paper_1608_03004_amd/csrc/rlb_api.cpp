@@ -533,6 +533,10 @@ rlb_status rlb_bind(rlb_lattice* L, void* workspace, size_t bytes, void* hip_str
   L->stream = static_cast<hipStream_t>(hip_stream);
   L->initialised = false;
   rlb_status st;
+  // the padding cells of the state rows (x >= nx) are never written by the
+  // kernels: start them, and everything else, at zero so that copies of a
+  // state are deterministic
+  HIP_TRY(L, hipMemsetAsync(L->ws, 0, L->total, L->stream));
   if ((st = upload(L, L->off_tubes, L->tubes.data(), L->tubes.size() * sizeof(TubeDev))) != RLB_OK) return st;
   if (L->prec == RLB_FP32) {
     if ((st = upload(L, L->off_jtab, L->jtab_f.data(), L->jtab_f.size() * 4)) != RLB_OK) return st;
@@ -868,20 +872,14 @@ rlb_status need_adjoint(rlb_lattice* L) {
 
 extern "C" {
 
-rlb_status rlb_adjoint_step(rlb_lattice* L, const void* state_n, void* lambda, double* dL_dtau) {
-  rlb_status st = need_adjoint(L);
-  if (st != RLB_OK) return st;
-  if (!state_n || !lambda || !dL_dtau) return fail(L, RLB_ERR_INVALID_ARG, "state_n, lambda and dL_dtau are required");
-  if (state_n == lambda) return fail(L, RLB_ERR_INVALID_ARG, "state_n and lambda must not alias");
-  void* F1 = L->ws + L->off_aF[0];
-  void* F2 = L->ws + L->off_aF[1];
-  double* r0 = L->dev<double>(L->off_arec[0]);
-  double* r1 = L->dev<double>(L->off_arec[1]);
-  double* r2 = L->dev<double>(L->off_arec[2]);
-  // recompute the two intermediate stages of the step from f^n
-  if ((st = moments_of(L, state_n, r0)) != RLB_OK) return st;
-  if ((st = run_stage(L, 1, state_n, state_n, F1, r0, r1)) != RLB_OK) return st;
-  if ((st = run_stage(L, 2, F1, state_n, F2, r1, r2)) != RLB_OK) return st;
+namespace {
+
+// The three adjoint stages of one step (f^n, its stage states f1, f2 and
+// their records given) and the dL/dtau reduction: lambda goes from
+// dL/df^{n+1} to dL/df^n.
+rlb_status adjoint_of_step(rlb_lattice* L, const void* Fn, const void* F1, const void* F2, const double* r0,
+                           const double* r1, const double* r2, void* lambda, double* dL_dtau) {
+  rlb_status st;
   void* lam2 = L->ws + L->off_lam2;
   void* lam1 = L->ws + L->off_lam1;
   void* acc = L->ws + L->off_acc;
@@ -904,12 +902,79 @@ rlb_status rlb_adjoint_step(rlb_lattice* L, const void* state_n, void* lambda, d
       // f2 = 3/4 f^n + 1/4 (f1 + dt L(f1))
       if ((st = stage(F1, r1, lam2, lam1, acc, acc, 0.25, 0.25 * dt, 0.75, 0, 0, 0)) != RLB_OK) return st;
       // f1 = f^n + dt L(f^n)
-      if ((st = stage(state_n, r0, lam1, lambda, acc, nullptr, 1.0, dt, 0.0, 1, 0, 0)) != RLB_OK) return st;
+      if ((st = stage(Fn, r0, lam1, lambda, acc, nullptr, 1.0, dt, 0.0, 1, 0, 0)) != RLB_OK) return st;
       hipError_t e = launch_tau_reduce(L->dev<TubeDev>(L->off_tubes), t, L->dev<double>(L->off_tauacc), dL_dtau,
                                        L->stream);
       if (e != hipSuccess) return hip_fail(L, e, "tau reduction launch");
     }
   }
+  return RLB_OK;
+}
+
+// Layout of one step in the segment scratch: f^n, f1, f2, then their records.
+struct SegmentStep {
+  size_t F[3], R[3], bytes;
+};
+
+SegmentStep segment_step(const rlb_lattice* L) {
+  SegmentStep s;
+  size_t o = 0;
+  for (int k = 0; k < 3; ++k) { s.F[k] = o; o = align256(o + L->state_elems * L->rsize); }
+  for (int k = 0; k < 3; ++k) { s.R[k] = o; o = align256(o + L->rec_elems * 8); }
+  s.bytes = o;
+  return s;
+}
+
+}  // namespace
+
+rlb_status rlb_adjoint_step(rlb_lattice* L, const void* state_n, void* lambda, double* dL_dtau) {
+  rlb_status st = need_adjoint(L);
+  if (st != RLB_OK) return st;
+  if (!state_n || !lambda || !dL_dtau) return fail(L, RLB_ERR_INVALID_ARG, "state_n, lambda and dL_dtau are required");
+  if (state_n == lambda) return fail(L, RLB_ERR_INVALID_ARG, "state_n and lambda must not alias");
+  void* F1 = L->ws + L->off_aF[0];
+  void* F2 = L->ws + L->off_aF[1];
+  double* r0 = L->dev<double>(L->off_arec[0]);
+  double* r1 = L->dev<double>(L->off_arec[1]);
+  double* r2 = L->dev<double>(L->off_arec[2]);
+  // recompute the two intermediate stages of the step from f^n
+  if ((st = moments_of(L, state_n, r0)) != RLB_OK) return st;
+  if ((st = run_stage(L, 1, state_n, state_n, F1, r0, r1)) != RLB_OK) return st;
+  if ((st = run_stage(L, 2, F1, state_n, F2, r1, r2)) != RLB_OK) return st;
+  return adjoint_of_step(L, state_n, F1, F2, r0, r1, r2, lambda, dL_dtau);
+}
+
+rlb_status rlb_adjoint_segment_size(const rlb_lattice* L, int32_t nsteps, size_t* bytes) {
+  if (!L || !bytes || nsteps < 1) return RLB_ERR_INVALID_ARG;
+  *bytes = segment_step(L).bytes * size_t(nsteps);
+  return RLB_OK;
+}
+
+rlb_status rlb_adjoint_segment(rlb_lattice* L, const void* state0, int32_t nsteps, void* scratch, size_t bytes,
+                               void* lambda, double* dL_dtau) {
+  rlb_status st = need_adjoint(L);
+  if (st != RLB_OK) return st;
+  if (!state0 || !scratch || !lambda || !dL_dtau || nsteps < 1)
+    return fail(L, RLB_ERR_INVALID_ARG, "state0, scratch, lambda, dL_dtau and nsteps >= 1 are required");
+  const SegmentStep ss = segment_step(L);
+  if (bytes < ss.bytes * size_t(nsteps)) return fail(L, RLB_ERR_INVALID_ARG, "scratch smaller than rlb_adjoint_segment_size");
+  char* base = static_cast<char*>(scratch);
+  auto F = [&](int k, int s) { return static_cast<void*>(base + size_t(k) * ss.bytes + ss.F[s]); };
+  auto R = [&](int k, int s) { return reinterpret_cast<double*>(base + size_t(k) * ss.bytes + ss.R[s]); };
+  // forward: f^n, f1, f2 of every step of the segment and their records
+  hipError_t e = launch_copy(F(0, 0), state0, L->state_elems * L->rsize, L->stream);
+  if (e != hipSuccess) return hip_fail(L, e, "state copy");
+  if ((st = moments_of(L, F(0, 0), R(0, 0))) != RLB_OK) return st;
+  for (int k = 0; k < nsteps; ++k) {
+    if ((st = run_stage(L, 1, F(k, 0), F(k, 0), F(k, 1), R(k, 0), R(k, 1))) != RLB_OK) return st;
+    if ((st = run_stage(L, 2, F(k, 1), F(k, 0), F(k, 2), R(k, 1), R(k, 2))) != RLB_OK) return st;
+    if (k + 1 < nsteps && (st = run_stage(L, 3, F(k, 2), F(k, 0), F(k + 1, 0), R(k, 2), R(k + 1, 0))) != RLB_OK)
+      return st;
+  }
+  // reverse
+  for (int k = nsteps - 1; k >= 0; --k)
+    if ((st = adjoint_of_step(L, F(k, 0), F(k, 1), F(k, 2), R(k, 0), R(k, 1), R(k, 2), lambda, dL_dtau)) != RLB_OK)
+      return st;
   return RLB_OK;
 }
 

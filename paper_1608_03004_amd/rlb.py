@@ -83,6 +83,8 @@ _SIGNATURES = {
     "rlb_tables": [_VP, ctypes.c_int32, _DP, _DP, _DP, _DP],
     "rlb_device_copy": [_VP, _VP, ctypes.c_size_t, _VP],
     "rlb_adjoint_step": [_VP, _VP, _VP, _VP],
+    "rlb_adjoint_segment_size": [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
+    "rlb_adjoint_segment": [_VP, _VP, ctypes.c_int32, _VP, ctypes.c_size_t, _VP, _VP],
     "rlb_fields_adjoint": [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_int64, _VP],
     "rlb_initial_state_adjoint": [_VP, ctypes.c_int32, _VP, _DP, _DP],
 }
@@ -305,6 +307,22 @@ def _lattice_adjoint_methods():
         self._check(self.lib.rlb_adjoint_step(self.h, _VP(state_n.data_ptr()), _VP(lam.data_ptr()),
                                               _VP(dL_dtau.data_ptr())))
 
+    def adjoint_segment_size(self, nsteps: int) -> int:
+        n = ctypes.c_size_t(0)
+        self._check(self.lib.rlb_adjoint_segment_size(self.h, int(nsteps), ctypes.byref(n)))
+        return n.value
+
+    def adjoint_segment(self, state0, nsteps: int, scratch, lam, dL_dtau):
+        """Reverse sweep over the nsteps steps that start from state0: lam goes from
+        dL/df^{n+nsteps} to dL/df^n in place, dL_dtau is incremented.  scratch: a
+        device uint8 tensor of at least adjoint_segment_size(nsteps) bytes."""
+        for t in (state0, lam):
+            assert t.dtype == self.dtype and t.is_contiguous() and t.numel() >= self.state_elems
+        assert scratch.is_contiguous() and scratch.element_size() == 1
+        assert dL_dtau.dtype.is_floating_point and dL_dtau.element_size() == 8 and dL_dtau.numel() >= len(self.tubes)
+        self._check(self.lib.rlb_adjoint_segment(self.h, _VP(state0.data_ptr()), int(nsteps), _VP(scratch.data_ptr()),
+                                                 scratch.numel(), _VP(lam.data_ptr()), _VP(dL_dtau.data_ptr())))
+
     def fields_adjoint(self, tube, state, dfields, lam):
         """Writes dL/df of a loss on the fields of `state` into tube's rows of lam."""
         assert dfields.element_size() == 8 and dfields.is_contiguous() and dfields.shape[0] == 10
@@ -318,6 +336,8 @@ def _lattice_adjoint_methods():
         return gl, gr
 
     Lattice.adjoint_step = adjoint_step
+    Lattice.adjoint_segment_size = adjoint_segment_size
+    Lattice.adjoint_segment = adjoint_segment
     Lattice.fields_adjoint = fields_adjoint
     Lattice.initial_state_adjoint = initial_state_adjoint
 

@@ -204,3 +204,33 @@ def test_fp32_adjoint_against_fp64_adjoint(torch_cuda):
     print(f"[adjoint fp32 vs fp64] {g32} {g64}", flush=True)
     scale = np.abs(g64).max()
     assert np.abs(g32 - g64).max() < 1e-3 * scale
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_adjoint_segment_equals_step_by_step_adjoint(torch_cuda, precision):
+    # One reverse sweep over a segment (stage states recomputed once and kept)
+    # against rlb_adjoint_step applied to each recomputed state in turn.
+    torch = torch_cuda
+    params = dict(nx=300, q_xi=12, q_p=3, tau=2e-2)
+    lat = _lattice([params], precision)
+    lat.set_initial_state((1.0, 1.0, 0.1), (0.2, 0.3, -0.1))
+    lat.step(4)
+    state0 = lat.get_state().clone()
+    nseg = 6
+    states = [state0]
+    for _ in range(nseg - 1):
+        lat.step(1)
+        states.append(lat.get_state().clone())
+    g = torch.Generator(device="cuda").manual_seed(3)
+    lam0 = torch.rand(lat.state_elems, dtype=lat.dtype, device="cuda", generator=g) - 0.5
+    lam_a, lam_b = lam0.clone(), lam0.clone()
+    da = torch.zeros(1, dtype=torch.float64, device="cuda")
+    db = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for F in reversed(states):
+        lat.adjoint_step(F, lam_a, da)
+    scratch = torch.empty(lat.adjoint_segment_size(nseg), dtype=torch.uint8, device="cuda")
+    lat.adjoint_segment(state0, nseg, scratch, lam_b, db)
+    torch.cuda.synchronize()
+    assert torch.equal(lam_a, lam_b) and torch.equal(da, db)
+    # the lattice's own state is untouched by the sweep
+    assert torch.equal(lat.tube_view(lat.get_state()), lat.tube_view(states[-1]))
