@@ -278,7 +278,7 @@ __global__ __launch_bounds__(256) void init_adjoint_partial_kernel(const TubeDev
   const TubeDev& tb = tubes[tube];
   const int y = blockIdx.x * blockDim.x + threadIdx.x;
   const bool valid = y < tb.nx;
-  const int side = valid ? ((tb.z_min + (y + 0.5) * tb.dz) < 0.0 ? 0 : 1) : 0;
+  const int side = valid ? (left_of_split(tb, y) ? 0 : 1) : 0;
   const Real* jtab = jtab_all + int64_t(tb.jrow) * kJStride;
   const Real* lam = lambda0 + tb.f_off;
   constexpr int NC = QPT * (NVT + 1);

@@ -60,6 +60,17 @@ struct Acc<float> {
   __device__ double value() const { return double(s) - double(c); }
 };
 
+// Initial condition (eq. condinit): cell x takes the left state when its
+// centre z_min + (x + 1/2) dz lies below z = 0 (a centre exactly at 0 takes
+// the right state).  The centre is formed with a separately rounded product
+// and sum, never a fused multiply-add, so that every cell falls on the same
+// side as in plain IEEE arithmetic.
+__device__ inline bool left_of_split(const TubeDev& tb, int x) {
+#pragma clang fp contract(off)
+  const double centre = tb.z_min + (double(x) + 0.5) * tb.dz;
+  return centre < 0.0;
+}
+
 struct Macro {
   double e, v, gamma, u, n, T;
   bool ok;

@@ -475,8 +475,7 @@ __global__ __launch_bounds__(TILE) void init_kernel(InitArgs<Real> a) {
     const TubeDev& tb = a.tubes[wi.tube];
     const int x = wi.x0 + t;
     if (x >= tb.nx) continue;
-    const double z = tb.z_min + (x + 0.5) * tb.dz;
-    const double* st = a.sides + 6 * wi.tube + (z < 0.0 ? 0 : 3);
+    const double* st = a.sides + 6 * wi.tube + (left_of_split(tb, x) ? 0 : 3);
     const double P = st[0], n = st[1], u = st[2];
     const double T = P / n, gamma = sqrt(1.0 + u * u);
     const Real* jtab = a.jtab + int64_t(tb.jrow) * kJStride;

@@ -177,6 +177,22 @@ def test_node_split_launch_matches_single_launch_bitwise(torch_cuda, precision):
             assert normwise(runs[0][k], F).max() < 1e-12
 
 
+def test_zero_steps_and_single_tile_tubes(torch_cuda):
+    # step(0) is a no-op; the smallest tubes (8 cells, one ragged tile) at both
+    # tile sizes follow the oracle.
+    params = [dict(nx=8, q_xi=4, q_p=3, tau=1e-2), dict(nx=9, q_xi=5, q_p=3, tau=1e-2)]
+    for tile in (128, 256):
+        lat = _lattice(params, schedule=dict(tile=tile))
+        lat.set_initial_state(SOD_L, SOD_R)
+        before = [lat.state_array(k) for k in range(2)]
+        lat.step(0)
+        assert all(np.array_equal(lat.state_array(k), before[k]) for k in range(2))
+        lat.step(6)
+        for k, p in enumerate(params):
+            F, ref = _oracle_run(p, SOD_L, SOD_R, 6)
+            assert normwise(lat.state_array(k), F).max() < 1e-12
+
+
 def test_set_state_round_trip(torch_cuda):
     params = dict(nx=400, q_xi=8, q_p=3, tau=1e-2)
     lat = _lattice([params])
@@ -264,6 +280,38 @@ def test_full_size_sod_large_fp32_window(torch_cuda):
 def test_full_size_ballistic_fp32_window(torch_cuda):
     # N_x = 2^22, Q = 256 x 4, tau = 1e3 (the ballistic stress configuration), FP32
     _window_check(dict(nx=1 << 22, q_xi=256, q_p=4, tau=1e3), "fp32", 2, tol=1e-5)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_maximum_tube_length(torch_cuda, precision, tol):
+    # nx = 2^26, the largest tube the library accepts (the chunk of rows a stage
+    # workgroup addresses then spans 2 GiB): the centre follows the oracle on a
+    # window, and both outflow ends still hold the undisturbed initial states.
+    torch = torch_cuda
+    from oracle import oracle as O
+    nx, nsteps, half = 1 << 26, 2, 128
+    params = dict(nx=nx, q_xi=4, q_p=3, tau=1e-2)
+    lat = _lattice([params], precision=precision)
+    lat.set_initial_state(SOD_L, SOD_R)
+    lat.step(nsteps)
+    f = lat.fields(0)
+    c, pad = nx // 2, 9 * nsteps
+    centre = f[:, c - half: c + half].cpu().numpy()
+    ends = torch.cat([f[:, :64], f[:, -64:]], dim=1).cpu().numpy()
+    dt, dz = lat.info(0)["dt"], 1.0 / nx
+    a, b = c - half - pad, c + half + pad
+    t = O.Tube(**dict(params, nx=b - a, z_min=-0.5 + a * dz, z_max=-0.5 + b * dz, dt=dt))
+    ref = O.fields(t, O.run(t, SOD_L, SOD_R, nsteps))
+    errs = field_errors(centre, ref[:, pad: pad + 2 * half])
+    _report(f"nx=2^26 {precision}", errs)
+    assert max(e[0] for e in errs.values()) < tol, errs
+    # undisturbed ends: the fields of the initial left and right states
+    te = O.Tube(nx=16, q_xi=4, q_p=3, tau=1e-2)
+    fl = O.fields(te, O.init(te, SOD_L, SOD_L))[:, 0]
+    fr = O.fields(te, O.init(te, SOD_R, SOD_R))[:, 0]
+    assert np.abs(ends[:, :64] - fl[:, None]).max() <= tol * np.abs(fl).max()
+    assert np.abs(ends[:, 64:] - fr[:, None]).max() <= tol * np.abs(fr).max()
+    del lat, f
 
 
 def test_autotuner_restores_state_and_keeps_results(torch_cuda, tmp_path):
