@@ -224,8 +224,20 @@ struct Moments3 {
   Acc<Real> a0, a1, a2;
 };
 
+// Waves per SIMD the register allocation must allow.  The first stage of a
+// step (no f^n stream) is limited by its arithmetic, and one more resident
+// wave per SIMD there outweighs the few registers it spills (measured on the
+// Q_p <= 4 groups: +1 % FP32, +2 % FP64 per step); stages 2 and 3 are
+// bandwidth-bound, and the Q_p = 8 group holds too many coefficients, so
+// they keep every value in registers.
+template <typename Real, int QPT, bool HAS_FN>
+constexpr int stage_waves_per_simd() {
+  return (HAS_FN || QPT > 4) ? 1 : (sizeof(Real) == 4 ? 5 : 4);
+}
+
 template <typename Real, int TILE, int QPT, int NVT, bool HAS_FN, int CH>
-__global__ __launch_bounds__(TILE) void stage_kernel(StageArgs<Real> a) {
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(stage_waves_per_simd<Real, QPT, HAS_FN>())))
+void stage_kernel(StageArgs<Real> a) {
   constexpr int V = LdsVec<Real>::V, NH = CH / V;
   static_assert(CH % V == 0, "a chunk is a whole number of 16-byte LDS words");
   using Vec = typename LdsVec<Real>::type;
