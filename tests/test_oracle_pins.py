@@ -94,10 +94,12 @@ def _perfect_fluid(n, T, u):
     return np.array([n * g, n * u, (e + P) * g * g - P, (e + P) * g * u, (e + P) * u * u + P])
 
 
-@pytest.mark.parametrize("qx,qp", [(4, 3), (6, 3), (8, 3), (8, 4), (64, 4), (5, 3)])
-def test_equilibrium_moments_are_perfect_fluid(qx, qp):
-    # N^mu = n u^mu and T^{mu nu} = (e+P) u^mu u^nu + P g^{mu nu} with e = 3nT.
-    tube = O.Tube(nx=4, q_xi=qx, q_p=qp)
+@pytest.mark.parametrize("qx,qp,nv", [(4, 3, 5), (6, 3, 5), (8, 3, 5), (8, 4, 5), (64, 4, 5), (5, 3, 5),
+                                      (9, 3, 8), (33, 3, 20), (64, 4, 63)])
+def test_equilibrium_moments_are_perfect_fluid(qx, qp, nv):
+    # N^mu = n u^mu and T^{mu nu} = (e+P) u^mu u^nu + P g^{mu nu} with e = 3nT,
+    # also for the high angular orders (N_v up to Q_xi - 1).
+    tube = O.Tube(nx=4, q_xi=qx, q_p=qp, n_v=nv, n_p=min(2, qp - 1))
     B = O.moments_weights(tube)
     rng = np.random.default_rng(1)
     for _ in range(20):
@@ -123,6 +125,14 @@ def test_rest_state_closed_form():
                         for pi in p])
         assert np.abs(F - ref[:, None]).max() < 1e-15
     assert np.abs(O.feq_nodes(tube, 1.0, 1.0, 0.0) - 0.25).max() < 1e-15
+    # the same holds at the highest angular order: every P_k, k >= 1, integrates to 0
+    high = O.Tube(nx=4, q_xi=64, q_p=3, n_v=63)
+    xi, wxi, p, wp = O.tables(high)
+    F = O.feq_nodes(high, 0.7, 1.7, 0.0).reshape(3, 64)
+    ref = np.array([0.7 / (4 * 1.7) * sum((1 - 1.7) ** l * sp.eval_genlaguerre(l, 1, pi) for l in range(3))
+                    for pi in p])
+    # (63 terms that vanish only up to rounding: a few ulps of the result)
+    assert np.abs(F - ref[:, None]).max() < 3e-14 * ref.max()
 
 
 def _brute_coefficient(n, T, u, k, l):
@@ -148,6 +158,23 @@ def test_projection_coefficients_brute_force():
             for l in range(3):
                 ref = _brute_coefficient(n, T, u, k, l)
                 assert abs(C[k, l] - ref) <= 1e-10 * max(abs(ref), 1e-3 * abs(C).max()), (k, l)
+
+
+def test_high_order_projection_coefficients_brute_force():
+    # Coefficients of high angular order (N_v = 63) at a fast flow, where they
+    # are far from negligible, against nested adaptive quadrature.
+    import warnings
+    tube = O.Tube(nx=4, q_xi=64, q_p=4, n_v=63)
+    n, T, v = 0.7, 0.9, 0.9
+    u = v / math.sqrt(1 - v * v)
+    C = O.feq_coefficients(tube, n, T, u)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", si.IntegrationWarning)
+        for k, rel in ((16, 1e-12), (31, 1e-9), (48, None)):
+            ref = _brute_coefficient(n, T, u, k, 1)
+            assert abs(C[k, 1] - ref) <= 1e-14 * np.abs(C).max(), k
+            if rel is not None:
+                assert abs(C[k, 1] - ref) <= rel * abs(ref), k
 
 
 def test_projection_k0_closed_forms():
@@ -193,6 +220,28 @@ def test_truncation_is_orthogonal_projection():
             basis = sp.eval_genlaguerre(l, 1, pr)[:, None] * sp.eval_legendre(k, xa)[None, :]
             resid = np.sum(wr[:, None] * wa[None, :] * (Feq - Ftr) * basis)
             assert abs(resid) < 1e-11
+
+
+@pytest.mark.parametrize("nv", [40, 63])
+def test_high_order_truncation_is_orthogonal_projection(nv):
+    # The defining property at high angular order: the residual F^eq - F_trunc
+    # is orthogonal to every L_l(p) P_k(xi), k <= N_v, on an independent
+    # 160 x 60 product rule.
+    tube = O.Tube(nx=4, q_xi=64, q_p=4, n_v=nv)
+    n, T, v = 0.8, 1.2, 0.6
+    u = v / math.sqrt(1 - v * v)
+    g = math.sqrt(1 + u * u)
+    C = O.feq_coefficients(tube, n, T, u)
+    xa, wa = np.polynomial.legendre.leggauss(160)
+    pr, wr = sp.roots_genlaguerre(60, 1)
+    Feq = n / (4 * T ** 3) * np.exp(pr[:, None] * (1 - (g - xa[None, :] * u) / T))
+    Pk = np.array([sp.eval_legendre(k, xa) for k in range(nv + 1)])
+    Ll = np.array([sp.eval_genlaguerre(l, 1, pr) for l in range(3)])
+    ck = (2 * np.arange(nv + 1) + 1) / 2
+    cl = 1 / (np.arange(3) + 1)
+    Ftr = np.einsum("kl,k,l,kx,lp->px", C, ck, cl, Pk, Ll)
+    resid = np.einsum("p,x,px,kx,lp->kl", wr, wa, Feq - Ftr, Pk, Ll)
+    assert np.abs(resid).max() < 1e-13
 
 
 # ---------------------------------------------------------------------------
