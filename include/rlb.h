@@ -73,9 +73,12 @@ typedef enum { RLB_FP64 = 0, RLB_FP32 = 1 } rlb_precision;
  *                space"; Q_p = 3 suffices for N^mu and T^{mu nu}, section
  *                Riemann problem); q_p <= 8;
  *   n_v, n_p  -- truncation orders of eq. feqtrunc (the paper uses 5 and 2);
- *                n_v <= 7 and n_p < q_p;  N^mu and T^{mu nu} of the
- *                equilibrium are exact when n_p + 2 <= 2 q_p - 1 and
- *                n_v + 2 <= 2 q_xi - 1, both required;
+ *                n_p < q_p;  n_v <= 7, or 7 < n_v < q_xi <= 64 (the
+ *                high-order form: the equilibrium is evaluated by a
+ *                matrix-core pre-pass into one more state-sized buffer; no
+ *                adjoint);  N^mu and T^{mu nu} of the equilibrium are exact
+ *                when n_p + 2 <= 2 q_p - 1 and n_v + 2 <= 2 q_xi - 1, both
+ *                required;
  *   tau       -- constant relaxation time (section Relativistic LB equation);
  *                +INFINITY gives the collisionless (ballistic) limit;
  *   dt        -- > 0: explicit time step; 0: min(cfl*dz, dt_tau_max*tau)
@@ -122,7 +125,8 @@ rlb_status rlb_tube_defaults(rlb_tube_desc* desc);
 /* Validates the tubes and builds the host tables; no device work.
  * tubes: ntubes >= 1 descriptors (copied).  prec: arithmetic of the
  * distribution (the Landau matching and the moment records are always FP64).
- * flags: RLB_WITH_ADJOINT or 0.  *out receives the handle. */
+ * flags: RLB_WITH_ADJOINT or 0 (RLB_WITH_ADJOINT with a tube of n_v > 7 is
+ * RLB_ERR_INVALID_ARG).  *out receives the handle. */
 rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision prec, uint32_t flags,
                       rlb_lattice** out);
 rlb_status rlb_destroy(rlb_lattice* lat);

@@ -47,6 +47,8 @@ struct rlb_lattice {
   std::vector<TubeDev> tubes;
   std::vector<double> jtab_d, itab, aux_d;
   std::vector<float> jtab_f, aux_f;
+  std::vector<double> ztab;  // high-order equilibrium tables (see high_order_table)
+  bool has_high = false;
   int aux_pairs = 0;
   std::vector<std::vector<double>> xi, wxi, p, wp;  // per tube (host copies)
 
@@ -57,6 +59,7 @@ struct rlb_lattice {
   size_t off_tubes = 0, off_jtab = 0, off_itab = 0, off_aux = 0, off_aux_d = 0, off_items = 0, off_sides = 0,
          off_mask = 0, off_flag = 0, off_fields = 0, off_totals = 0, total = 0;
   size_t off_part = 0;  // per-node sums of split launches (0: none)
+  size_t off_ztab = 0, off_feq = 0;  // high-order tables and equilibrium values (0: none)
   int part_stride = 0;  // doubles per cell in that buffer
   // adjoint workspace (RLB_WITH_ADJOINT)
   int64_t cell_elems = 0, face_elems = 0;
@@ -108,7 +111,8 @@ rlb_status hip_fail(rlb_lattice* L, hipError_t e, const char* where) {
   } while (0)
 
 void kernel_group(int qp, int nv, int* qpt, int* nvt) {
-  if (nv <= 5 && qp <= 3) { *qpt = 3; *nvt = 5; }
+  if (nv > kMaxNv) { *qpt = 8; *nvt = kNvtHigh; }
+  else if (nv <= 5 && qp <= 3) { *qpt = 3; *nvt = 5; }
   else if (nv <= 5 && qp == 4) { *qpt = 4; *nvt = 5; }
   else { *qpt = 8; *nvt = 7; }
 }
@@ -117,6 +121,40 @@ double tube_dt(const rlb_tube_desc& d) {
   const double dz = (d.z_max - d.z_min) / d.nx;
   if (d.dt > 0) return d.dt;
   return std::min(d.cfl * dz, d.dt_tau_max * d.tau);
+}
+
+// Table of the high-order equilibrium of a tube with q_xi polar nodes xi
+// (ascending, symmetric) and truncation n_v: Ze and Zo [zj][zb] with
+//   Ze[j][b] = 2 w_b sum_{k <= n_v even} (2k+1)/2 P_k(x_b) P_k(xi_j),
+//   Zo[j][b] = 2 w_b sum_{k <= n_v odd}  (2k+1)/2 P_k(x_b) P_k(xi_j)
+// for the nodes xi_j <= 0 (j < ceil(q_xi/2); the rows up to zj are zero),
+// then the positive nodes x_b of the 2 zb-point Gauss-Legendre rule with
+// weights w_b.  Sums in extended precision.
+void high_order_table(int qx, int nv, const std::vector<double>& xi, std::vector<double>& out) {
+  const int zj = high_rows(qx), zb = high_aux_pairs(nv), half = (qx + 1) / 2;
+  std::vector<double> ax, aw;
+  gauss_legendre_rule(2 * zb, ax, aw);
+  std::vector<double> t(size_t(2 * zj + 1) * zb, 0.0);
+  for (int b = 0; b < zb; ++b) {
+    const long double x = ax[zb + b], w = aw[zb + b];
+    t[size_t(2 * zj) * zb + b] = ax[zb + b];
+    for (int j = 0; j < half; ++j) {
+      const long double y = xi[j];
+      long double px0 = 1.0L, px1 = x, py0 = 1.0L, py1 = y;  // P_k, P_{k+1} at x and y
+      long double se = 0.0L, so = 0.0L;
+      for (int k = 0; k <= nv; ++k) {
+        const long double term = (2.0L * k + 1.0L) / 2.0L * px0 * py0;
+        if (k & 1) so += term; else se += term;
+        const long double px2 = ((2.0L * k + 3.0L) * x * px1 - (k + 1.0L) * px0) / (k + 2.0L);
+        const long double py2 = ((2.0L * k + 3.0L) * y * py1 - (k + 1.0L) * py0) / (k + 2.0L);
+        px0 = px1; px1 = px2;
+        py0 = py1; py1 = py2;
+      }
+      t[size_t(j) * zb + b] = double(2.0L * w * se);
+      t[size_t(zj + j) * zb + b] = double(2.0L * w * so);
+    }
+  }
+  out.insert(out.end(), t.begin(), t.end());
 }
 
 rlb_status validate(const rlb_tube_desc& d, int k, std::string& msg) {
@@ -130,7 +168,11 @@ rlb_status validate(const rlb_tube_desc& d, int k, std::string& msg) {
   if (d.nx < 8 || d.nx > (1 << 26)) return bad("nx must be in [8, 2^26]");
   if (d.q_xi < 1 || d.q_xi > 4096) return bad("q_xi must be in [1, 4096]");
   if (d.q_p < 1 || d.q_p > kMaxQp) return bad("q_p must be in [1, 8]");
-  if (d.n_v < 0 || d.n_v > kMaxNv) return bad("n_v must be in [0, 7]");
+  if (d.n_v < 0 || d.n_v > kMaxNvHigh) return bad("n_v must be in [0, 63]");
+  // the high-order form (n_v > 7) keeps q_xi <= 64 and, as the quadrature
+  // section requires of the truncation, n_v < q_xi
+  if (d.n_v > kMaxNv && (d.q_xi > kMaxQxHigh || d.n_v >= d.q_xi))
+    return bad("n_v > 7 needs n_v < q_xi <= 64");
   if (d.n_p < 0 || d.n_p >= d.q_p) return bad("n_p must satisfy 0 <= n_p < q_p");
   if (d.n_p + 2 > 2 * d.q_p - 1) return bad("q_p too small to integrate T^{mu nu} of the equilibrium exactly");
   if (d.n_v + 2 > 2 * d.q_xi - 1) return bad("q_xi too small to integrate T^{mu nu} of the equilibrium exactly");
@@ -213,8 +255,34 @@ LaunchShape shape(const rlb_lattice* L, const Group& g) {
   return ls;
 }
 
+// High-order equilibrium pre-pass of one kernel group: F_eq of the state whose
+// records are `rec`, or with rec == nullptr of the masked tubes' initial side
+// states, into `out`.  Large groups take one workgroup per tile for all radial
+// nodes (the tables are staged once per tile); small ones spread the nodes
+// over a second grid dimension.
+template <typename Real>
+hipError_t equilibrium_pass(rlb_lattice* L, const Group& g, const double* rec, void* out, hipStream_t s) {
+  FeqArgs<Real> f;
+  f.tubes = L->dev<TubeDev>(L->off_tubes);
+  f.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
+  f.nitems = g.item_end - g.item_begin;
+  f.tile = L->sched.tile;
+  f.itab = L->dev<double>(L->off_itab);
+  f.ztab = L->dev<double>(L->off_ztab);
+  f.rec = rec;
+  f.sides = L->dev<double>(L->off_sides);
+  f.tube_mask = L->dev<int32_t>(L->off_mask);
+  f.out = static_cast<Real*>(out);
+  LaunchShape ls;
+  ls.tile = L->sched.tile;
+  ls.grid = f.nitems;
+  ls.nodes = f.nitems < 2 * std::max(1, L->cu_count) ? g.qp_max : 1;
+  return launch_feq(sizeof(Real) == 4, ls, &f, s);
+}
+
 // One SSP-RK3 stage of one kernel group with explicit buffers: the stage
-// kernel and, for a split launch, the kernel that forms the records.
+// kernel (after the equilibrium pre-pass for the high-order group) and, for a
+// split launch, the kernel that forms the records.
 template <typename Real>
 hipError_t stage_group(rlb_lattice* L, const Group& g, int stage, const void* fin, const void* fn, void* fout,
                        const double* rec_in, double* rec_out, hipStream_t s) {
@@ -236,7 +304,14 @@ hipError_t stage_group(rlb_lattice* L, const Group& g, int stage, const void* fi
   a.flag = L->dev<unsigned>(L->off_flag);
   a.part = ls.nodes > 1 ? L->dev<double>(L->off_part) : nullptr;
   a.part_stride = L->part_stride;
-  hipError_t e = launch_stage(sizeof(Real) == 4, g.qpt, g.nvt, ls, &a, s);
+  a.feq = nullptr;
+  hipError_t e = hipSuccess;
+  if (g.nvt == kNvtHigh) {
+    a.feq = L->dev<Real>(L->off_feq);
+    e = equilibrium_pass<Real>(L, g, rec_in, L->ws + L->off_feq, s);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_stage(sizeof(Real) == 4, g.qpt, g.nvt, ls, &a, s);
   if (e == hipSuccess && ls.nodes > 1)
     e = launch_combine(a.tubes, a.items, a.nitems, ls.tile, a.itab, a.part, a.part_stride, rec_out, s);
   return e;
@@ -348,6 +423,8 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
     std::string msg;
     rlb_status st = validate(tubes[k], k, msg);
     if (st != RLB_OK) return fail(nullptr, st, msg);
+    if ((flags & RLB_WITH_ADJOINT) && tubes[k].n_v > kMaxNv)
+      return fail(nullptr, RLB_ERR_INVALID_ARG, "the adjoint supports n_v <= 7 only");
   }
   rlb_lattice* L = new rlb_lattice();
   L->desc.assign(tubes, tubes + ntubes);
@@ -362,6 +439,7 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
   // quadrature tables, shared between tubes with equal orders
   std::map<int, int> jrow_of;                          // q_xi -> first row
   std::map<std::tuple<int, double>, int> irow_of;      // (q_p, T0) -> first row
+  std::map<std::pair<int, int>, int64_t> zoff_of;      // (q_xi, n_v) -> high-order table
   L->xi.resize(ntubes); L->wxi.resize(ntubes); L->p.resize(ntubes); L->wp.resize(ntubes);
   int64_t f_off = 0, rec_off = 0;
   for (int t = 0; t < ntubes; ++t) {
@@ -424,6 +502,18 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
     td.tau_inv = 1.0 / d.tau;
     td.T0 = d.T0;
     td.weno_eps = d.weno_eps;
+    if (d.n_v > kMaxNv) {
+      const auto key = std::make_pair(d.q_xi, d.n_v);
+      auto zt = zoff_of.find(key);
+      if (zt == zoff_of.end()) {
+        zt = zoff_of.emplace(key, int64_t(L->ztab.size())).first;
+        high_order_table(d.q_xi, d.n_v, x, L->ztab);
+      }
+      td.z_off = zt->second;
+      td.zj = high_rows(d.q_xi);
+      td.zb = high_aux_pairs(d.n_v);
+      L->has_high = true;
+    }
     int qpt, nvt;
     kernel_group(d.q_p, d.n_v, &qpt, &nvt);
     td.group = qpt * 16 + nvt;
@@ -479,6 +569,10 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
   L->off_flag = o; o = align256(o + 16);
   L->off_fields = o; o = align256(o + 10 * size_t(L->max_ldx) * 8);
   L->off_totals = o; o = align256(o + 4 * 8);
+  if (L->has_high) {
+    L->off_ztab = o; o = align256(o + L->ztab.size() * 8);
+    L->off_feq = o; o = align256(o + L->state_elems * L->rsize);
+  }
   if (L->cell_elems <= kSplitMaxCells) {
     int qp_max = 1;
     for (auto& d : L->desc) qp_max = std::max(qp_max, d.q_p);
@@ -548,6 +642,7 @@ rlb_status rlb_bind(rlb_lattice* L, void* workspace, size_t bytes, void* hip_str
   if ((st = upload(L, L->off_itab, L->itab.data(), L->itab.size() * 8)) != RLB_OK) return st;
   if ((st = upload(L, L->off_aux_d, L->aux_d.data(), L->aux_d.size() * 8)) != RLB_OK) return st;
   if ((st = upload(L, L->off_items, L->items.data(), L->items.size() * sizeof(WorkItem))) != RLB_OK) return st;
+  if ((st = upload(L, L->off_ztab, L->ztab.data(), L->ztab.size() * 8)) != RLB_OK) return st;
   HIP_TRY(L, hipMemsetAsync(L->ws + L->off_flag, 0, 16, L->stream));
   HIP_TRY(L, hipStreamSynchronize(L->stream));
   return RLB_OK;
@@ -595,7 +690,18 @@ rlb_status launch_init_all(rlb_lattice* L) {
   for (const Group& g : L->groups) {
     LaunchShape ls = shape(L, g);
     hipError_t e;
-    if (fp32) {
+    if (g.nvt == kNvtHigh) {
+      // the equilibrium of the side states, then the records of the state
+      // (records of unmasked tubes are recomputed from their state: equal to
+      // the bit)
+      void* f0 = L->ws + L->off_F[0];
+      e = fp32 ? equilibrium_pass<float>(L, g, nullptr, f0, L->stream)
+               : equilibrium_pass<double>(L, g, nullptr, f0, L->stream);
+      if (e == hipSuccess)
+        e = launch_moments(fp32 ? 1 : 0, L->dev<TubeDev>(L->off_tubes), L->dev<WorkItem>(L->off_items) + g.item_begin,
+                           g.item_end - g.item_begin, L->sched.tile, L->ws + L->off_jtab, L->dev<double>(L->off_itab),
+                           f0, L->dev<double>(L->off_rec[0]), L->stream);
+    } else if (fp32) {
       InitArgs<float> a;
       a.tubes = L->dev<TubeDev>(L->off_tubes);
       a.items = L->dev<WorkItem>(L->off_items) + g.item_begin;

@@ -22,6 +22,26 @@ constexpr int kAuxStride = 10;
 constexpr int kAuxPairsFP64 = 24;  // 48-point Gauss-Legendre rule
 constexpr int kAuxPairsFP32 = 12;  // 24-point Gauss-Legendre rule
 
+// High-order equilibrium (kMaxNv < n_v <= kMaxNvHigh, q_xi <= kMaxQxHigh):
+// the equilibrium of a cell is evaluated by a pre-pass on the matrix cores
+// (rlb_feq.hip) as
+//   F_eq(p_i, xi_j) = pref sum_a G_i(x_a) Z(x_a, xi_j),
+//   Z(x, xi) = w(x) sum_{k <= n_v} (2k+1)/2 P_k(x) P_k(xi),
+// over an auxiliary Gauss-Legendre rule of 2B points +-x_b, in even/odd form:
+// with E_b = G(+x_b) + G(-x_b), O_b = G(+x_b) - G(-x_b) and j' the mirror node
+// of j (xi_j' = -xi_j),
+//   F_j + F_j' = sum_b E_b Ze[j][b],  F_j - F_j' = sum_b O_b Zo[j][b],
+//   Ze[j][b] = Z(x_b, xi_j) + Z(x_b, -xi_j),  Zo[j][b] = Z(x_b, xi_j) - Z(x_b, -xi_j).
+constexpr int kMaxNvHigh = 63;        // angular truncation limit of that form
+constexpr int kMaxQxHigh = 64;        // polar order limit of that form
+constexpr int kNvtHigh = -1;          // kernel-group tag of that form
+constexpr int kHighExtraPoints = 48;  // auxiliary points beyond n_v
+// B: pairs of the auxiliary rule (2B >= n_v + kHighExtraPoints), a multiple of
+// the MFMA's K = 4
+constexpr int high_aux_pairs(int nv) { return 4 * ((nv + kHighExtraPoints + 7) / 8); }
+// rows of Ze, Zo: ceil(q_xi / 2) rounded up to the MFMA's M = 16 (zero rows)
+constexpr int high_rows(int qx) { return 16 * (((qx + 1) / 2 + 15) / 16); }
+
 // Sticky device flags.
 constexpr unsigned kFlagNonphysical = 1u;
 constexpr unsigned kFlagFastFlow = 2u;  // |v| > 0.95: projection rule less accurate
@@ -37,6 +57,11 @@ struct TubeDev {
   int32_t ldf;      // row stride of the adjoint face buffer (>= nx + 1)
   int64_t cell_off; // offset of the tube in per-cell arrays (sum of ldx of earlier tubes)
   int64_t face_off; // element offset of the tube in one slot of the adjoint face buffer
+  // high-order equilibrium table (double offset into the table buffer):
+  // Ze [zj][zb], then Zo [zj][zb], then the positive nodes x_b [zb];
+  // zj = high_rows(q_xi), zb = high_aux_pairs(n_v)
+  int64_t z_off;
+  int32_t zj, zb;
 };
 
 // Arguments of the adjoint kernels of one stage of one tube.  For the stage
@@ -95,6 +120,24 @@ struct StageArgs {
   // written by the stage kernel
   double* part;
   int32_t part_stride;
+  const Real* feq;  // high-order group: the stage input's equilibrium (state layout)
+};
+
+// Arguments of the high-order equilibrium pre-pass: F_eq of the state whose
+// moment records are `rec` (or, with rec == nullptr, of the initial side
+// states of the tubes whose tube_mask is set) into `out` (state layout).
+template <typename Real>
+struct FeqArgs {
+  const TubeDev* tubes;
+  const WorkItem* items;
+  int32_t nitems;
+  int32_t tile;
+  const double* itab;
+  const double* ztab;
+  const double* rec;
+  const double* sides;
+  const int32_t* tube_mask;
+  Real* out;
 };
 
 template <typename Real>
@@ -129,6 +172,7 @@ hipError_t launch_fields(const TubeDev* tubes, int tube, int nx, const double* r
                          unsigned* flag, hipStream_t stream);
 hipError_t launch_totals(const TubeDev* tubes, int tube, const double* rec, double* out, hipStream_t stream);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+hipError_t launch_feq(int prec_fp32, const LaunchShape& ls, const void* args, hipStream_t stream);
 hipError_t launch_combine(const TubeDev* tubes, const WorkItem* items, int nitems, int tile, const double* itab,
                           const double* part, int part_stride, double* rec_out, hipStream_t stream);
 

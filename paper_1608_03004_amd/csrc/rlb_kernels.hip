@@ -13,6 +13,8 @@
 //   2. solves the Landau matching in FP64;
 //   3. projects the Maxwell-Juettner equilibrium onto the truncated basis with
 //      an auxiliary Gauss-Legendre rule (coefficients D[i][k] in registers);
+//      the high-order group (n_v > 7) instead streams the equilibrium values
+//      that the matrix-core pre-pass of rlb_feq.hip wrote for this stage;
 //   4. streams over the quadrature points in chunks of CH points: the chunk's
 //      F values of the tile plus a 3-cell halo go to LDS (16-byte words of
 //      consecutive chunk points of one cell), each lane computes the WENO5
@@ -233,6 +235,11 @@ __global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(stage_wave
 void stage_kernel(StageArgs<Real> a) {
   constexpr int V = LdsVec<Real>::V, NH = CH / V;
   static_assert(CH % V == 0, "a chunk is a whole number of 16-byte LDS words");
+  // NVT < 0: high-order group, whose equilibrium values are read from a.feq
+  // (written for this stage's input by the equilibrium pre-pass) instead of
+  // being evaluated from projection coefficients
+  constexpr bool kHigh = NVT < 0;
+  constexpr int ND = kHigh ? 1 : NVT + 1;
   using Vec = typename LdsVec<Real>::type;
   __shared__ __attribute__((aligned(16))) Real tile[NH][TILE + 6][V];
   __shared__ __attribute__((aligned(16))) Real faces[NH][TILE + 1][V];
@@ -256,6 +263,7 @@ void stage_kernel(StageArgs<Real> a) {
     const int64_t f_off = tbp->f_off;
     const Real* fin = a.fin + f_off;
     const Real* fn = a.fn + f_off;
+    const Real* feq_t = a.feq + f_off;
     Real* fout = a.fout + f_off;
     const cptr<Real> jtab = as_const(a.jtab) + int64_t(tbp->jrow) * kJStride;
     const cptr<double> itab = as_const(a.itab) + int64_t(tbp->irow) * kIStride;
@@ -281,9 +289,10 @@ void stage_kernel(StageArgs<Real> a) {
     if (valid && fabs(M.v) > 0.95) raise_flag(a.flag, kFlagFastFlow);
 
     // 3. equilibrium coefficients
-    Real D[QPT][NVT + 1];
-    feq_coefficients<Real, QPT, NVT>(Real(M.n), Real(M.T), Real(M.gamma), Real(M.u), Real(tbp->T0), qp, tbp->np,
-                                     tbp->nv, itab, as_const(a.aux), a.aux_pairs, D);
+    Real D[QPT][ND];
+    if constexpr (!kHigh)
+      feq_coefficients<Real, QPT, NVT>(Real(M.n), Real(M.T), Real(M.gamma), Real(M.u), Real(tbp->T0), qp, tbp->np,
+                                       tbp->nv, itab, as_const(a.aux), a.aux_pairs, D);
     // out = cn f^n + cs f_in + cs dt L,  L = -xi/dz (F_+ - F_-) - (gamma - xi u)/tau (f - f^eq)
     const int stage = a.stage;
     const Real cn = stage == 1 ? Real(0) : (stage == 2 ? Real(0.75) : Real(1.0 / 3.0));
@@ -302,6 +311,12 @@ void stage_kernel(StageArgs<Real> a) {
         const ChunkRows<Real, CH> rows(fn, ldx, row_bytes, qx, i, j0);
 #pragma unroll
         for (int c = 0; c < CH; ++c) nr[c] = BufIO<Real>::template load<kFnAux>(rows.r, vx, rows.soff(c, row_bytes));
+      }
+      Real er[kHigh ? CH : 1];
+      if constexpr (kHigh) {
+        const ChunkRows<Real, CH> rows(feq_t, ldx, row_bytes, qx, i, j0);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) er[c] = BufIO<Real>::template load<kFnAux>(rows.r, vx, rows.soff(c, row_bytes));
       }
       {  // next chunk: the next radial node's first at the end of a node; the
          // very last chunk re-loads itself
@@ -386,9 +401,14 @@ void stage_kernel(StageArgs<Real> a) {
             const int c = h * V + e;
             if (decltype(full)::value || c < cj) {
               const cptr<Real> J = jtab + (j0 + c) * kJStride;
-              Real feq = Dc[0];
+              Real feq;
+              if constexpr (kHigh) {
+                feq = er[c];
+              } else {
+                feq = Dc[0];
 #pragma unroll
-              for (int kk = 1; kk <= NVT; ++kk) feq += Dc[kk] * J[4 + kk];
+                for (int kk = 1; kk <= NVT; ++kk) feq += Dc[kk] * J[4 + kk];
+              }
               const Real fr = wf[e];
               const Real df = fr - feq;
               const Real adv = (wr[e] - wl[e]) * (-J[0] * dz_inv);
@@ -428,13 +448,15 @@ void stage_kernel(StageArgs<Real> a) {
     // register buffers so that no in-flight load is ever copied
 #pragma unroll 1
     for (int i = i_first; i < i_last; ++i) {
-      Real Dc[NVT + 1];
+      Real Dc[ND] = {};
+      if constexpr (!kHigh) {
 #pragma unroll
-      for (int k = 0; k <= NVT; ++k) {
-        Real d = D[0][k];
+        for (int k = 0; k < ND; ++k) {
+          Real d = D[0][k];
 #pragma unroll
-        for (int ii = 1; ii < QPT; ++ii) d = i == ii ? D[ii][k] : d;
-        Dc[k] = d;
+          for (int ii = 1; ii < QPT; ++ii) d = i == ii ? D[ii][k] : d;
+          Dc[k] = d;
+        }
       }
       Moments3<Real> acc;
       for (int j0 = 0; j0 < qx; j0 += 2 * CH) {
@@ -638,6 +660,7 @@ hipError_t launch_stage_real(int qpt, int nvt, const LaunchShape& ls, const void
   if (qpt == 3 && nvt == 5) return launch_stage_tile<Real, 3, 5>(ls, args, s);
   if (qpt == 4 && nvt == 5) return launch_stage_tile<Real, 4, 5>(ls, args, s);
   if (qpt == 8 && nvt == 7) return launch_stage_tile<Real, 8, 7>(ls, args, s);
+  if (qpt == 8 && nvt == kNvtHigh) return launch_stage_tile<Real, 8, kNvtHigh>(ls, args, s);
   return hipErrorInvalidValue;
 }
 

@@ -46,7 +46,9 @@ def test_defaults_are_the_papers(lib):
     (dict(q_p=9), rlb.RLB_ERR_INVALID_ARG),
     (dict(n_p=3, q_p=3), rlb.RLB_ERR_INVALID_ARG),
     (dict(q_p=2, n_p=1, n_v=5, q_xi=2), rlb.RLB_ERR_INVALID_ARG),   # q_xi too small for T^{mu nu}
-    (dict(n_v=8), rlb.RLB_ERR_INVALID_ARG),
+    (dict(n_v=8), rlb.RLB_ERR_INVALID_ARG),                          # high-order form needs n_v < q_xi
+    (dict(n_v=64, q_xi=64), rlb.RLB_ERR_INVALID_ARG),
+    (dict(n_v=20, q_xi=65), rlb.RLB_ERR_INVALID_ARG),               # ... and q_xi <= 64
     (dict(tau=0.0), rlb.RLB_ERR_INVALID_ARG),
     (dict(tau=-1.0), rlb.RLB_ERR_INVALID_ARG),
     (dict(T0=0.0), rlb.RLB_ERR_INVALID_ARG),
@@ -90,6 +92,31 @@ def test_valid_create_and_host_queries(lib):
     assert lib.rlb_tube_info(h, 3, None, None, None) == rlb.RLB_ERR_INVALID_ARG
     assert lib.rlb_set_tau(h, 0, -1.0) == rlb.RLB_ERR_INVALID_ARG
     assert lib.rlb_destroy(h) == 0
+
+
+def test_high_order_tubes_create_without_adjoint(lib):
+    # 7 < n_v < q_xi <= 64: the matrix-core equilibrium form; it adds one
+    # state-sized equilibrium buffer to the workspace and has no adjoint
+    low = [rlb.Tube(nx=300, q_xi=64, q_p=4)]
+    high = [rlb.Tube(nx=300, q_xi=64, q_p=4, n_v=63), rlb.Tube(nx=50, q_xi=9, q_p=2, n_v=8, n_p=1)]
+    st, h = _create(lib, low)
+    assert st == 0
+    base = ctypes.c_size_t()
+    lib.rlb_workspace_size(h, ctypes.byref(base))
+    lib.rlb_destroy(h)
+    st, h = _create(lib, high[:1])
+    assert st == 0, lib.rlb_last_error(None)
+    size = ctypes.c_size_t()
+    lib.rlb_workspace_size(h, ctypes.byref(size))
+    assert size.value >= base.value + 256 * 320 * 8
+    lib.rlb_destroy(h)
+    arr = (rlb.TubeDesc * 2)(*[t.c() for t in high])
+    h = ctypes.c_void_p()
+    assert lib.rlb_create(arr, 2, rlb.RLB_FP32, 0, ctypes.byref(h)) == 0
+    lib.rlb_destroy(h)
+    h = ctypes.c_void_p()
+    assert lib.rlb_create(arr, 2, rlb.RLB_FP64, rlb.RLB_WITH_ADJOINT, ctypes.byref(h)) == rlb.RLB_ERR_INVALID_ARG
+    assert not h.value and b"n_v <= 7" in lib.rlb_last_error(None)
 
 
 @pytest.mark.parametrize("q_xi,q_p", [(2, 3), (5, 3), (8, 3), (64, 4), (128, 3), (200, 5), (256, 4)])

@@ -314,6 +314,70 @@ def test_maximum_tube_length(torch_cuda, precision, tol):
     del lat, f
 
 
+# ---------------------------------------------------------------------------
+# High-order equilibrium (7 < N_v < Q_xi <= 64): matrix-core pre-pass
+# ---------------------------------------------------------------------------
+HIGH_CASES = [
+    dict(nx=300, q_xi=64, q_p=4, n_v=63, tau=1e-2),             # largest form, ragged last tile
+    dict(nx=200, q_xi=33, q_p=3, n_v=20, tau=5e-3),             # odd q_xi (xi = 0 node), zero table rows
+    dict(nx=9, q_xi=9, q_p=3, n_v=8, tau=2e-2),                 # smallest high-order tube
+    dict(nx=130, q_xi=16, q_p=8, n_v=15, n_p=3, tau=1e-1),      # q_p = 8 (n_p <= 3: radial series well conditioned)
+]
+MOVING_L, MOVING_R = (1.0, 1.0, 0.4), (0.3, 0.5, -0.6)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+@pytest.mark.parametrize("params", HIGH_CASES, ids=[f"high{k}" for k in range(len(HIGH_CASES))])
+def test_high_order_equilibrium_against_oracle(torch_cuda, params, precision, tol):
+    # moving states exercise the odd Legendre orders; the initial state is the
+    # pre-pass's output for the side states, the steps its output for the
+    # Landau frame of every stage input
+    from oracle import oracle as O
+    lat = _lattice([params], precision=precision)
+    lat.set_initial_state(MOVING_L, MOVING_R)
+    t = oracle_tube(params)
+    assert normwise(lat.state_array(0), O.init(t, MOVING_L, MOVING_R)).max() < tol
+    lat.step(20)
+    F, ref = _oracle_run(params, MOVING_L, MOVING_R, 20)
+    errs = field_errors(lat.moments(0), ref)
+    _report(f"high n_v={params['n_v']} q_xi={params['q_xi']} {precision}", errs)
+    assert max(e[0] for e in errs.values()) < tol, errs
+    assert normwise(lat.state_array(0), F).max() < tol
+
+
+def test_high_order_batched_with_low_order_tubes_and_schedules(torch_cuda):
+    # one lattice holding high- and low-order groups; every schedule (tile,
+    # persistent grid, graph replay) gives the same bits and the oracle's values
+    plist = [HIGH_CASES[1], dict(nx=300, q_xi=8, q_p=3, tau=1e-2), HIGH_CASES[0],
+             dict(nx=100, q_xi=32, q_p=3, n_v=31, tau=1e-2)]
+    lefts = [MOVING_L, (1.0, 1.0, 0.0), SOD_L, (2.0, 1.5, 0.2)]
+    rights = [MOVING_R, (0.1, 0.125, 0.0), SOD_R, (0.1, 0.125, -0.1)]
+    states = None
+    for sched in (dict(tile=256), dict(tile=128, persistent=1, blocks_per_cu=1), dict(tile=256, graph_steps=4)):
+        lat = _lattice(plist, schedule=sched)
+        lat.set_initial_states(lefts, rights)
+        lat.step(12)
+        got = [lat.state_array(k) for k in range(len(plist))]
+        if states is None:
+            states = got
+            for k, p in enumerate(plist):
+                F, ref = _oracle_run(p, lefts[k], rights[k], 12)
+                errs = field_errors(lat.moments(k), ref)
+                assert max(e[0] for e in errs.values()) < 1e-12, (k, errs)
+                assert normwise(got[k], F).max() < 1e-12
+        else:
+            for a, b in zip(got, states):
+                assert np.array_equal(a, b), sched
+        del lat
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_full_size_high_order_window(torch_cuda, precision, tol):
+    # N_x = 2^18, Q = 64 x 4, N_v = 63: enough tiles that the pre-pass takes all
+    # radial nodes per workgroup and the stage kernel is not split
+    _window_check(dict(nx=1 << 18, q_xi=64, q_p=4, n_v=63, tau=1e-2), precision, 3, tol=tol)
+
+
 def test_autotuner_restores_state_and_keeps_results(torch_cuda, tmp_path):
     from paper_1608_03004_amd import autotune
     import workloads
