@@ -14,6 +14,8 @@ whole tube.  Beside it, on the same line:
   adjoint     gradient of the profile loss of the 4096-cell, Q = 32 x 3 tube
               over 2000 steps (forward + sqrt(N)-checkpointed backward);
   ballistic   the 2^22-cell, Q = 256 x 4 tube at tau = 1e3 (FP32);
+  high        the headline tube with the high-order equilibrium (N_v = 63),
+              FP32 and FP64, with the matrix-core roofline of its pre-pass;
   roofline    of the stage kernel: algorithmic bytes per launch over its mean
               duration, timed with HIP events on the launch stream;
   cpu_baseline the CPU FP64 oracle on a bounded sample of the headline tube.
@@ -207,6 +209,60 @@ def leg_ballistic(steps, warmup=2):
     return out
 
 
+MFMA_F64_PEAK_TFS = 78.6  # MI355X dense FP64 matrix
+
+
+def high_order_flops(tube):
+    """Algorithmic flops of one equilibrium pre-pass over a high-order tube:
+    per cell and radial node the two even/odd products, ceil(q_xi/2) rows by
+    B auxiliary pairs, one multiply and one add each."""
+    B = 4 * ((tube.n_v + 89 + 15) // 16)
+    return 4 * ((tube.q_xi + 1) // 2) * B * tube.nx * tube.q_p
+
+
+def leg_high_order(precision, steps, warmup=2, reps=10):
+    """The large Sod tube with the high-order equilibrium (N_v = 63 = Q_xi - 1):
+    every stage runs the matrix-core pre-pass and then the stage kernel that
+    streams its output."""
+    import torch
+    from paper_1608_03004_amd import Lattice, Tube
+    tube = Tube(nx=1 << 20, q_xi=64, q_p=4, n_v=63, tau=1e-2)
+    lat = Lattice([tube], precision=precision)
+    lat.set_initial_state(SOD_L, SOD_R)
+    lat.step(warmup)
+    lat.check()
+    wall, ev = timed_steps(lat, steps)
+    lat.check()
+    # the pre-pass alone on the lattice's stream (same launch as inside a stage)
+    out = lat.new_state()
+    lat.equilibrium(out)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(lat.stream)
+    for _ in range(reps):
+        lat.equilibrium(out)
+    stop.record(lat.stream)
+    torch.cuda.synchronize()
+    feq_s = start.elapsed_time(stop) * 1e-3 / reps
+    rsize = 4 if precision == "fp32" else 8
+    flops = high_order_flops(tube)
+    stage_s = ev / steps / 3 - feq_s
+    # stage kernel bytes: the low-order stage's streams plus the equilibrium read
+    stage_bytes = step_bytes([tube], rsize) / 3 + tube.nx * tube.Q * rsize
+    res = dict(value=tube.nx * tube.Q * steps / wall, unit="cell*quad-point updates/s",
+               ms_per_step=1e3 * wall / steps, steps=steps,
+               roofline=dict(bound="mfma", achieved=round(flops / feq_s / 1e12, 2), peak=MFMA_F64_PEAK_TFS,
+                             unit="TFLOP/s", frac=round(flops / feq_s / 1e12 / MFMA_F64_PEAK_TFS, 4), traffic=None,
+                             kernel="feq_kernel", flops_per_launch=flops, launch_us=round(feq_s * 1e6, 2)),
+               stage_roofline=dict(bound="hbm", achieved=round(stage_bytes / stage_s / 1e9, 1), peak=HBM_PEAK_GBS,
+                                   unit="GB/s", frac=round(stage_bytes / stage_s / 1e9 / HBM_PEAK_GBS, 4),
+                                   bytes_per_launch=int(stage_bytes), launch_us=round(stage_s * 1e6, 2)),
+               workload=f"sod_large_high_order: N_x=2^20, Q=64x4, N_v=63, N_p=2, tau=1e-2, {precision.upper()}")
+    del lat, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def leg_copy(nbytes=1 << 30, reps=5):
     """Plain device-to-device copy through the library's copy kernel: the
     practical HBM ceiling, and the calibration of the HBM byte counters."""
@@ -260,8 +316,10 @@ def main():
     ap.add_argument("--tile", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"),
                     help="form of the headline tube (fp64 is for profiling runs; the headline is fp32)")
-    ap.add_argument("--legs", default="fp64,batched,adjoint,ballistic,copy,cpu",
-                    help="comma-separated extra legs (fp64, batched, adjoint, ballistic, copy, cpu) or 'none'")
+    ap.add_argument("--legs", default="fp64,batched,adjoint,ballistic,high,copy,cpu",
+                    help="comma-separated extra legs (fp64, batched, adjoint, ballistic, high, copy, cpu) "
+                         "or 'none'")
+    ap.add_argument("--high-steps", type=int, default=20)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--ballistic-steps", type=int, default=20)
     args = ap.parse_args()
@@ -308,6 +366,9 @@ def main():
         line["adjoint"] = dict(fp64=leg_adjoint("fp64"), fp32=leg_adjoint("fp32"))
     if "ballistic" in legs:
         line["ballistic"] = leg_ballistic(args.ballistic_steps)
+    if "high" in legs:
+        line["high_order"] = dict(fp32=leg_high_order("fp32", args.high_steps),
+                                  fp64=leg_high_order("fp64", args.high_steps))
     if "copy" in legs:
         line["copy"] = leg_copy()
     if "cpu" in legs:

@@ -173,6 +173,18 @@ rlb_status rlb_state_layout(const rlb_lattice* lat, int32_t tube, int64_t* off, 
 rlb_status rlb_get_state(rlb_lattice* lat, void* dst_device);
 rlb_status rlb_set_state(rlb_lattice* lat, const void* src_device);
 
+/* Truncated equilibrium (eq. feqtrunc, truncated at N_p and N_v) of the
+ * current state, in the Landau frame of each cell's moments, for the tubes
+ * of the high-order form (n_v > 7): dst_device (device memory, state layout
+ * and precision of the lattice, rlb_state_elems elements, caller-owned)
+ * receives F_eq at every quadrature point of those tubes' cells; the entries
+ * of other tubes and of padding cells are left untouched.  It is the pre-pass
+ * that each stage runs on its input (matrix cores, FP64 arithmetic, rounded
+ * to the lattice's precision).  Asynchronous on the lattice's stream.
+ * RLB_ERR_INVALID_ARG if dst_device is NULL or no tube has n_v > 7;
+ * RLB_ERR_STATE without a bound workspace and a state. */
+rlb_status rlb_equilibrium(rlb_lattice* lat, void* dst_device);
+
 /* Per-tube parameters and time. */
 rlb_status rlb_set_tau(rlb_lattice* lat, int32_t tube, double tau);
 rlb_status rlb_tube_info(const rlb_lattice* lat, int32_t tube, double* dt, double* time, int32_t* Q);

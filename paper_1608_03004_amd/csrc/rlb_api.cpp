@@ -862,6 +862,21 @@ rlb_status rlb_get_state(rlb_lattice* L, void* dst) {
   return RLB_OK;
 }
 
+rlb_status rlb_equilibrium(rlb_lattice* L, void* dst) {
+  rlb_status st = need_ready(L, true);
+  if (st != RLB_OK) return st;
+  if (!dst) return fail(L, RLB_ERR_INVALID_ARG, "dst is NULL");
+  if (!L->has_high) return fail(L, RLB_ERR_INVALID_ARG, "no tube of the high-order form (n_v > 7)");
+  const double* rec = L->dev<double>(L->off_rec[0]);
+  for (const Group& g : L->groups) {
+    if (g.nvt != kNvtHigh) continue;
+    const hipError_t e = L->prec == RLB_FP32 ? equilibrium_pass<float>(L, g, rec, dst, L->stream)
+                                             : equilibrium_pass<double>(L, g, rec, dst, L->stream);
+    if (e != hipSuccess) return hip_fail(L, e, "equilibrium kernel launch");
+  }
+  return RLB_OK;
+}
+
 rlb_status rlb_set_state(rlb_lattice* L, const void* src) {
   rlb_status st = need_ready(L, false);
   if (st != RLB_OK) return st;

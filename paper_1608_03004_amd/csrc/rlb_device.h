@@ -65,11 +65,12 @@ struct Acc<float> {
 // the right state).  The centre is formed with a separately rounded product
 // and sum, never a fused multiply-add, so that every cell falls on the same
 // side as in plain IEEE arithmetic.
-__device__ inline bool left_of_split(const TubeDev& tb, int x) {
+__device__ inline bool left_of_split(double z_min, double dz, int x) {
 #pragma clang fp contract(off)
-  const double centre = tb.z_min + (double(x) + 0.5) * tb.dz;
+  const double centre = z_min + (double(x) + 0.5) * dz;
   return centre < 0.0;
 }
+__device__ inline bool left_of_split(const TubeDev& tb, int x) { return left_of_split(tb.z_min, tb.dz, x); }
 
 struct Macro {
   double e, v, gamma, u, n, T;

@@ -27,8 +27,15 @@
 // b = 4s + l / 16, which is the B-operand layout of the MFMA (B[k][n] in lane
 // 16k + n); the A operands Ze, Zo (A[m][k] in lane 16k + m) are staged in LDS
 // once per tile; result register r of lane l is row 4r + l / 16, column
-// l % 16.
+// l % 16.  Each K-step's E_b, O_b (two reciprocals, two Horner chains over
+// the node's Laguerre values, held in scalar registers for a compile-time
+// N_p) are formed just before the four products that consume them: FP64
+// vector instructions do not issue while the FP64 matrix pipe is busy, so a
+// step costs its products plus that vector work, and the register budget is
+// capped at 128 so that four waves per SIMD keep the matrix pipe fed.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "rlb_device.h"
 #include "rlb_internal.h"
@@ -43,106 +50,128 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kMaxS = high_aux_pairs(kMaxNvHigh) / 4;             // MFMA K-steps
 constexpr int kMaxZj = high_rows(kMaxQxHigh);                      // rows of Ze, Zo
 constexpr int kLdsLd = 4 * kMaxS + 1;                              // padded LDS row (doubles)
+static_assert(kMaxZj <= 32, "the kernel holds two row tiles of accumulators");
+
+// 1/d for d > 0 (normal): hardware reciprocal refined by two Newton steps
+// (the error of each step is the square of the previous one's).
+__device__ inline double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  r = fma(r, fma(-d, r, 1.0), r);
+  r = fma(r, fma(-d, r, 1.0), r);
+  return r;
+}
 
 template <typename Real>
-__global__ __launch_bounds__(256) void feq_kernel(FeqArgs<Real> a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void feq_kernel(FeqArgs<Real> a) {
   __shared__ double zs[2 * kMaxZj * kLdsLd + 4 * kMaxS];  // Ze rows, Zo rows, x_b
   const int t = threadIdx.x, w = t / 64, l = t % 64, col = l % 16, quarter = l / 16;
+  const cptr<WorkItem> items = as_const(a.items);
+  const cptr<TubeDev> tubes = as_const(a.tubes);
+  const cptr<double> itab = as_const(a.itab);
   for (int item = blockIdx.x; item < a.nitems; item += gridDim.x) {
-    const WorkItem wi = a.items[item];
-    const TubeDev& tb = a.tubes[wi.tube];
-    if (a.rec == nullptr && !a.tube_mask[wi.tube]) continue;
-    if (int(blockIdx.y) >= tb.qp) continue;
-    const int zj = tb.zj, zb = tb.zb, ns = zb / 4, ld = zb + 1;
+    const int wtube = items[item].tube, wx0 = items[item].x0;
+    const cptr<TubeDev> tb = tubes + wtube;
+    if (a.rec == nullptr && !as_const(a.tube_mask)[wtube]) continue;
+    const int qp = tb->qp, nx = tb->nx;
+    if (int(blockIdx.y) >= qp) continue;
+    const int zj = tb->zj, zb = tb->zb, ns = zb / 4, ld = zb + 1;
     __syncthreads();  // the previous item's reads of zs are done
-    const double* zt = a.ztab + tb.z_off;
+    const double* zt = a.ztab + tb->z_off;
     for (int e = t; e < 2 * zj * zb; e += blockDim.x) zs[(e / zb) * ld + e % zb] = zt[e];
     double* xs = zs + 2 * zj * ld;
     for (int e = t; e < zb; e += blockDim.x) xs[e] = zt[2 * zj * zb + e];
     __syncthreads();
-    const int np = tb.np, qx = tb.qx, half = (qx + 1) / 2;
-    const double T0 = tb.T0;
-    const int64_t ldx = tb.ldx;
-    Real* out = a.out + tb.f_off;
+    const int np = tb->np, qx = tb->qx, half = (qx + 1) / 2, njt = zj / 16, irow = tb->irow;
+    const double T0 = tb->T0, z_min = tb->z_min, dz = tb->dz;
+    const int64_t ldx = tb->ldx, rec_off = tb->rec_off;
+    Real* out = a.out + tb->f_off;
     for (int c0 = 16 * w; c0 < a.tile; c0 += 64) {
-      if (wi.x0 + c0 >= tb.nx) break;  // wave-uniform
-      const int x = wi.x0 + c0 + col;
-      const bool valid = x < tb.nx;
-      const int xc = valid ? x : tb.nx - 1;
+      if (wx0 + c0 >= nx) break;  // wave-uniform
+      const int x = wx0 + c0 + col;
+      const bool valid = x < nx;
+      const int xc = valid ? x : nx - 1;
       // macroscopic state of the cell: the Landau frame of its record, or the
       // initial state of its side
       double n, T, gam, u;
       if (a.rec != nullptr) {
         double m[5];
 #pragma unroll
-        for (int c = 0; c < 5; ++c) m[c] = a.rec[tb.rec_off + c * ldx + xc];
+        for (int c = 0; c < 5; ++c) m[c] = a.rec[rec_off + c * ldx + xc];
         const Macro M = landau(m);
         n = M.n;
         T = M.T;
         gam = M.gamma;
         u = M.u;
       } else {
-        const double* st = a.sides + 6 * wi.tube + (left_of_split(tb, xc) ? 0 : 3);
+        const cptr<double> st = as_const(a.sides) + 6 * wtube + (left_of_split(z_min, dz, xc) ? 0 : 3);
         n = st[1];
         T = st[0] / st[1];
         u = st[2];
         gam = sqrt(1.0 + u * u);
       }
       const double r = T / T0, pref = n / (4.0 * T * T0 * T0);
-      // y at +-x_b for this lane's pairs b = 4s + quarter (shared by all nodes)
-      double yp[kMaxS], ym[kMaxS];
+      for (int node = blockIdx.y; node < qp; node += gridDim.y) {
+        const cptr<double> Lrow = itab + int64_t(irow + node) * kIStride + 4;  // L_l(p_node)
+        // two row tiles of Ze / Zo at most (q_xi <= 64): four accumulators
+        d4 ce0 = {0.0, 0.0, 0.0, 0.0}, co0 = ce0, ce1 = ce0, co1 = ce0;
+        const double* ae = zs + col * ld + quarter;
+        const double* ao = ae + zj * ld;
+        // the node's products for a compile-time radial order NP (the
+        // Laguerre values of the node held in registers)
+        auto products = [&](auto np_c) {
+          constexpr int NP = decltype(np_c)::value;
+          double Lv[NP + 1];
 #pragma unroll
-      for (int s = 0; s < kMaxS; ++s) {
-        yp[s] = 0.0;
-        ym[s] = 0.0;
-        if (s < ns) {
-          const double xb = xs[4 * s + quarter];
-          yp[s] = 1.0 / (gam - xb * u);
-          ym[s] = 1.0 / (gam + xb * u);
-        }
-      }
-      for (int node = blockIdx.y; node < tb.qp; node += gridDim.y) {
-        const double* Lrow = a.itab + int64_t(tb.irow + node) * kIStride + 4;  // L_l(p_node)
-        double E[kMaxS], O[kMaxS];
-#pragma unroll
-        for (int s = 0; s < kMaxS; ++s) {
-          E[s] = 0.0;
-          O[s] = 0.0;
-          if (s < ns) {
-            const double qpl = 1.0 - r * yp[s], qmi = 1.0 - r * ym[s];
-            double sp = Lrow[np], sm = Lrow[np];
-            for (int k = np - 1; k >= 0; --k) {
-              sp = sp * qpl + Lrow[k];
-              sm = sm * qmi + Lrow[k];
-            }
-            const double gp = yp[s] * yp[s] * sp, gm = ym[s] * ym[s] * sm;
-            E[s] = pref * (gp + gm);
-            O[s] = pref * (gp - gm);
-          }
-        }
-        Real* orow = out + x;
-        for (int jt = 0; jt < zj / 16; ++jt) {
-          d4 ce = {0.0, 0.0, 0.0, 0.0}, co = {0.0, 0.0, 0.0, 0.0};
-          const double* ae = zs + (jt * 16 + col) * ld + quarter;
-          const double* ao = ae + zj * ld;
+          for (int k = 0; k <= NP; ++k) Lv[k] = Lrow[k];
 #pragma unroll
           for (int s = 0; s < kMaxS; ++s) {
             if (s < ns) {
-              ce = __builtin_amdgcn_mfma_f64_16x16x4f64(ae[4 * s], E[s], ce, 0, 0, 0);
-              co = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[4 * s], O[s], co, 0, 0, 0);
+              // B operands of this K-step: E_b, O_b of pair b = 4s + quarter
+              const double xb = xs[4 * s + quarter];
+              const double yp = recip(gam - xb * u), ym = recip(gam + xb * u);
+              const double qpl = 1.0 - r * yp, qmi = 1.0 - r * ym;
+              double sp = Lv[NP], sm = Lv[NP];
+#pragma unroll
+              for (int k = NP - 1; k >= 0; --k) {
+                sp = sp * qpl + Lv[k];
+                sm = sm * qmi + Lv[k];
+              }
+              const double gp = yp * yp * sp, gm = ym * ym * sm;
+              const double E = pref * (gp + gm), O = pref * (gp - gm);
+              ce0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ae[4 * s], E, ce0, 0, 0, 0);
+              co0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[4 * s], O, co0, 0, 0, 0);
+              if (njt > 1) {
+                ce1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ae[16 * ld + 4 * s], E, ce1, 0, 0, 0);
+                co1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[16 * ld + 4 * s], O, co1, 0, 0, 0);
+              }
             }
           }
-          if (valid) {
+        };
+        switch (np) {
+          case 0: products(std::integral_constant<int, 0>{}); break;
+          case 1: products(std::integral_constant<int, 1>{}); break;
+          case 2: products(std::integral_constant<int, 2>{}); break;
+          case 3: products(std::integral_constant<int, 3>{}); break;
+          case 4: products(std::integral_constant<int, 4>{}); break;
+          case 5: products(std::integral_constant<int, 5>{}); break;
+          case 6: products(std::integral_constant<int, 6>{}); break;
+          default: products(std::integral_constant<int, 7>{}); break;
+        }
+        if (valid) {
+          Real* orow = out + int64_t(node * qx) * ldx + x;
+          auto put = [&](const d4& ce, const d4& co, int jt) {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
               const int j = jt * 16 + 4 * rr + quarter;
               if (j < half) {
                 const int jm = qx - 1 - j;
-                orow[int64_t(node * qx + j) * ldx] = Real(0.5 * (ce[rr] + co[rr]));
-                if (jm != j) orow[int64_t(node * qx + jm) * ldx] = Real(0.5 * (ce[rr] - co[rr]));
+                orow[int64_t(j) * ldx] = Real(0.5 * (ce[rr] + co[rr]));
+                if (jm != j) orow[int64_t(jm) * ldx] = Real(0.5 * (ce[rr] - co[rr]));
               }
             }
-          }
+          };
+          put(ce0, co0, 0);
+          if (njt > 1) put(ce1, co1, 1);
         }
       }
     }

@@ -35,10 +35,12 @@ constexpr int kAuxPairsFP32 = 12;  // 24-point Gauss-Legendre rule
 constexpr int kMaxNvHigh = 63;        // angular truncation limit of that form
 constexpr int kMaxQxHigh = 64;        // polar order limit of that form
 constexpr int kNvtHigh = -1;          // kernel-group tag of that form
-constexpr int kHighExtraPoints = 48;  // auxiliary points beyond n_v
-// B: pairs of the auxiliary rule (2B >= n_v + kHighExtraPoints), a multiple of
-// the MFMA's K = 4
-constexpr int high_aux_pairs(int nv) { return 4 * ((nv + kHighExtraPoints + 7) / 8); }
+// B: pairs of the auxiliary rule, a multiple of the MFMA's K = 4, with
+// 2 (2B) - n_v >= kHighExactMargin: the rule integrates P_k G for k <= n_v
+// with the margin of degree that the 48-point rule of the low-order FP64
+// form has at n_v = 7 (96 - 7), so the two forms are equally accurate
+constexpr int kHighExactMargin = 89;
+constexpr int high_aux_pairs(int nv) { return 4 * ((nv + kHighExactMargin + 15) / 16); }
 // rows of Ze, Zo: ceil(q_xi / 2) rounded up to the MFMA's M = 16 (zero rows)
 constexpr int high_rows(int qx) { return 16 * (((qx + 1) / 2 + 15) / 16); }
 

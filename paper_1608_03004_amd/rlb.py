@@ -78,6 +78,7 @@ _SIGNATURES = {
     "rlb_state_layout": [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
     "rlb_get_state": [_VP, _VP],
     "rlb_set_state": [_VP, _VP],
+    "rlb_equilibrium": [_VP, _VP],
     "rlb_set_tau": [_VP, ctypes.c_int32, ctypes.c_double],
     "rlb_tube_info": [_VP, ctypes.c_int32, _DP, _DP, ctypes.POINTER(ctypes.c_int32)],
     "rlb_tables": [_VP, ctypes.c_int32, _DP, _DP, _DP, _DP],
@@ -263,6 +264,18 @@ class Lattice:
     def set_state(self, src):
         assert src.numel() >= self.state_elems and src.dtype == self.dtype and src.is_contiguous()
         self._check(self.lib.rlb_set_state(self.h, _VP(src.data_ptr())))
+
+    def equilibrium(self, out=None):
+        """Truncated equilibrium of the current state for the tubes with
+        n_v > 7 (flat state layout; other tubes' entries of ``out`` are left
+        as they are, zeros for a new tensor)."""
+        if out is None:
+            torch = _torch()
+            with torch.cuda.stream(self.stream):
+                out = torch.zeros(self.state_elems, dtype=self.dtype, device=self.device)
+        assert out.numel() >= self.state_elems and out.dtype == self.dtype and out.is_contiguous()
+        self._check(self.lib.rlb_equilibrium(self.h, _VP(out.data_ptr())))
+        return out
 
     def tube_view(self, state, tube: int = 0):
         """View [Q, nx] of one tube inside a flat state tensor."""
