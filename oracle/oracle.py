@@ -105,6 +105,14 @@ def _load():
         lib.oracle_init_tangent.argtypes = [tp, _State, _State, _State, _State, dp, dp]
         lib.oracle_fields_tangent.argtypes = [tp, dp, dp, dp, dp]
         lib.oracle_num_threads.restype = ctypes.c_int
+        pp = ctypes.POINTER(_Plane)
+        lib.oracle_plane_tables.argtypes = [pp, dp, dp]
+        lib.oracle_landau2d.argtypes = [dp, dp]
+        lib.oracle_plane_feq_nodes.argtypes = [pp] + [ctypes.c_double] * 4 + [dp]
+        lib.oracle_plane_init.argtypes = [pp, dp, dp]
+        lib.oracle_plane_step.argtypes = [pp, dp, ctypes.c_int64]
+        lib.oracle_plane_rhs.argtypes = [pp, dp, dp]
+        lib.oracle_plane_fields.argtypes = [pp, dp, dp]
         _lib = lib
     return _lib
 
@@ -254,3 +262,146 @@ def moments_weights(tube: Tube) -> np.ndarray:
 SOD_LEFT = (1.0, 1.0, 0.0)
 SOD_RIGHT = (0.1, 0.125, 0.0)
 PI = math.pi
+
+
+# ---------------------------------------------------------------------------
+# Multi-dimensional model on a plane (x, z)
+# ---------------------------------------------------------------------------
+class _Plane(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
+                ("z_min", ctypes.c_double), ("z_max", ctypes.c_double),
+                ("q_xi", ctypes.c_int32), ("q_phi", ctypes.c_int32), ("q_p", ctypes.c_int32),
+                ("n_v", ctypes.c_int32), ("n_p", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("dt", ctypes.c_double), ("T0", ctypes.c_double),
+                ("weno_eps", ctypes.c_double)]
+
+
+@dataclass
+class Plane:
+    """A 2D (x, z) domain with the full momentum quadrature (Q_p x Q_xi x Q_phi;
+    the evolved azimuthal nodes are k = 0 .. Q_phi // 2).
+
+    ``dt`` defaults to ``min(cfl / (1/dx + 1/dz), dt_tau_max * tau)``.
+    """
+    nx: int = 32
+    nz: int = 32
+    q_xi: int = 8
+    q_phi: int = 8
+    q_p: int = 3
+    n_v: int = 5
+    n_p: int = 2
+    tau: float = 1e-2
+    x_min: float = -0.5
+    x_max: float = 0.5
+    z_min: float = -0.5
+    z_max: float = 0.5
+    cfl: float = 0.5
+    dt_tau_max: float = 0.5
+    dt: float = 0.0
+    T0: float = 1.0
+    weno_eps: float = 1e-6
+
+    @property
+    def dx(self) -> float:
+        return (self.x_max - self.x_min) / self.nx
+
+    @property
+    def dz(self) -> float:
+        return (self.z_max - self.z_min) / self.nz
+
+    @property
+    def step_dt(self) -> float:
+        if self.dt > 0:
+            return self.dt
+        return min(self.cfl / (1.0 / self.dx + 1.0 / self.dz), self.dt_tau_max * self.tau)
+
+    @property
+    def q_h(self) -> int:
+        return self.q_phi // 2 + 1
+
+    @property
+    def Q(self) -> int:
+        return self.q_p * self.q_xi * self.q_h
+
+    def centres(self):
+        x = self.x_min + (np.arange(self.nx) + 0.5) * self.dx
+        z = self.z_min + (np.arange(self.nz) + 0.5) * self.dz
+        return x, z
+
+    def _c(self) -> _Plane:
+        return _Plane(self.nx, self.nz, self.x_min, self.x_max, self.z_min, self.z_max, self.q_xi, self.q_phi,
+                      self.q_p, self.n_v, self.n_p, self.tau, self.step_dt, self.T0, self.weno_eps)
+
+
+def plane_tables(plane: Plane):
+    """(cos phi_k, omega_k) of the evolved azimuthal nodes."""
+    c = np.zeros(plane.q_h); w = np.zeros(plane.q_h)
+    _check(_load().oracle_plane_tables(ctypes.byref(plane._c()), _ptr(c), _ptr(w)))
+    return c, w
+
+
+def landau2d(m):
+    """(N0, Nx, Nz, T00, T0x, T0z, Txx, Txz, Tzz) -> dict(e, vx, vz, gamma, n, T)."""
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    out = np.zeros(6)
+    _load().oracle_landau2d(_ptr(m), _ptr(out))
+    return dict(zip(("e", "vx", "vz", "gamma", "n", "T"), out))
+
+
+def plane_feq_nodes(plane: Plane, n: float, T: float, ux: float, uz: float) -> np.ndarray:
+    F = np.zeros(plane.Q)
+    _check(_load().oracle_plane_feq_nodes(ctypes.byref(plane._c()), n, T, ux, uz, _ptr(F)))
+    return F
+
+
+def plane_init(plane: Plane, fields: np.ndarray) -> np.ndarray:
+    """F[Q, nz, nx] from per-cell states fields[4, nz, nx] = (P, n, u^x, u^z)."""
+    f = np.ascontiguousarray(fields, dtype=np.float64)
+    assert f.shape == (4, plane.nz, plane.nx)
+    F = np.zeros((plane.Q, plane.nz, plane.nx))
+    _check(_load().oracle_plane_init(ctypes.byref(plane._c()), _ptr(f), _ptr(F)))
+    return F
+
+
+def plane_step(plane: Plane, F: np.ndarray, nsteps: int) -> np.ndarray:
+    G = np.array(F, dtype=np.float64, order="C", copy=True)
+    _check(_load().oracle_plane_step(ctypes.byref(plane._c()), _ptr(G), int(nsteps)))
+    return G
+
+
+def plane_rhs(plane: Plane, F: np.ndarray) -> np.ndarray:
+    G = np.ascontiguousarray(F, dtype=np.float64)
+    out = np.zeros_like(G)
+    _check(_load().oracle_plane_rhs(ctypes.byref(plane._c()), _ptr(G), _ptr(out)))
+    return out
+
+
+def plane_fields(plane: Plane, F: np.ndarray) -> np.ndarray:
+    """Per-cell fields [14, nz, nx]: N0, Nx, Nz, T00, T0x, T0z, Txx, Txz, Tzz, e, n, vx, vz, T."""
+    G = np.ascontiguousarray(F, dtype=np.float64)
+    out = np.zeros((14, plane.nz, plane.nx))
+    _check(_load().oracle_plane_fields(ctypes.byref(plane._c()), _ptr(G), _ptr(out)))
+    return out
+
+
+def plane_moments_weights(plane: Plane) -> np.ndarray:
+    """Moment basis B[9, Q]: the 9 moments of a cell = B @ F[:, z, x]."""
+    xi, wxi, p, wp = tables(Tube(nx=8, q_xi=plane.q_xi, q_p=plane.q_p, n_v=plane.n_v, n_p=plane.n_p,
+                                 T0=plane.T0))
+    cphi, om = plane_tables(plane)
+    B = np.zeros((9, plane.Q))
+    t3, t4 = plane.T0 ** 3, plane.T0 ** 4
+    for i in range(plane.q_p):
+        for j in range(plane.q_xi):
+            for k in range(plane.q_h):
+                s = (i * plane.q_xi + j) * plane.q_h + k
+                w = wp[i] * wxi[j] * om[k]
+                vx, vz = math.sqrt(1 - xi[j] ** 2) * cphi[k], xi[j]
+                a3, a4 = t3 * p[i] * w, t4 * p[i] ** 2 * w
+                B[:, s] = [a3, a3 * vx, a3 * vz, a4, a4 * vx, a4 * vz, a4 * vx * vx, a4 * vx * vz, a4 * vz * vz]
+    return B
+
+
+def plane_run(plane: Plane, fields: np.ndarray, nsteps: int) -> np.ndarray:
+    return plane_step(plane, plane_init(plane, fields), nsteps)

@@ -588,3 +588,305 @@ int oracle_num_threads(void) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Multi-dimensional model on a plane (x, z).
+//
+// The general equation (eq. Boltz_gen, with v = p/p^0 resolved in both
+// directions of the plane) reads, for the weight-free F:
+//   dF/dt = -v_x dF/dx - v_z dF/dz - ((u^0 - v_x u^x - v_z u^z)/tau) (F - F^eq),
+// with v = (sin(theta) cos(phi), sin(theta) sin(phi), cos(theta)) and the
+// full product quadrature of the section on the discretization of momentum
+// space: Gauss-Laguerre in p, Gauss-Legendre in xi = cos(theta) and the
+// trapezoid rule in phi (eq. azimuthInt) with nodes phi_k = 2 pi k / Q_phi
+// [reading: the printed nodes are garbled; any periodic trapezoid grid is
+// exact below Q_phi].  Nothing depends on y, and data with u^y = 0 stay
+// symmetric under phi -> -phi, so the nodes k and Q_phi - k carry equal values
+// and only k = 0 .. Q_phi/2 are evolved, with weights omega_k = m_k / Q_phi
+// (m_k = 2 for a mirrored pair, 1 otherwise; sum omega_k = 1) [reading].
+// F keeps the normalisation of the 1D oracle (2 pi e^p f), so a plane with no
+// x dependence reproduces the 1D tube.
+//
+// Point s = (i * Q_xi + j) * Q_h + k, Q_h = Q_phi/2 + 1 (integer division);
+// F[s][z][x].  Moments per cell (9; the y components vanish):
+//   N0, Nx, Nz   = T0^3 sum w p   {1, v_x, v_z} F
+//   T00, T0x, T0z, Txx, Txz, Tzz = T0^4 sum w p^2 {1, v_x, v_z, v_x^2, v_x v_z, v_z^2} F
+// with w = w_p w_xi omega.
+//
+// The Landau frame is the timelike eigenvector of T^mu_nu (T^mu_nu u^nu =
+// -e u^mu); -e is the eigenvalue of largest magnitude (the other eigenvalues
+// are the principal pressures, and e >= each of them for a massless gas), so
+// the power method converges to it.  With u = gamma (1, v) one power step is
+//   v_i <- (T^{0i} - T^{ij} v_j) / (T^{00} - T^{0j} v_j).
+//
+// Equilibrium: f^eq depends on the direction only through c = v . u_hat
+// (u_hat = u/|u|), so its orthogonal projection onto the polynomials of degree
+// <= N_v in v (the span of the vector polynomials of eq. feqtrunc) is the
+// Legendre series in c (Funk-Hecke), with the coefficients of the 1D
+// projection taken at the speed |u| [reading]:
+//   F_trunc(p_i, v) = sum_l sum_k (2k+1)/2 / (l+1) C_kl(|u|) P_k(c) L_l(p_i).
+// ===========================================================================
+
+extern "C" {
+struct oracle_plane {
+  int32_t nx, nz;           // cells along x and z, cell-centred
+  double x_min, x_max, z_min, z_max;
+  int32_t q_xi, q_phi, q_p; // quadrature orders
+  int32_t n_v, n_p;         // truncation orders
+  double tau, dt, T0, weno_eps;
+};
+}
+
+namespace {
+
+struct PlaneTables {
+  Tables t1;                      // polar and radial rules, projection rule
+  int qh;                         // evolved azimuthal nodes
+  std::vector<double> cphi, omega, sth;
+  static oracle_tube as_tube(const oracle_plane& p) {
+    oracle_tube t;
+    std::memset(&t, 0, sizeof t);
+    t.nx = p.nx;
+    t.z_min = p.z_min;
+    t.z_max = p.z_max;
+    t.q_xi = p.q_xi;
+    t.q_p = p.q_p;
+    t.n_v = p.n_v;
+    t.n_p = p.n_p;
+    t.tau = p.tau;
+    t.dt = p.dt;
+    t.T0 = p.T0;
+    t.weno_eps = p.weno_eps;
+    return t;
+  }
+  explicit PlaneTables(const oracle_plane& p) : t1(as_tube(p)), qh(p.q_phi / 2 + 1) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    cphi.resize(qh);
+    omega.resize(qh);
+    for (int k = 0; k < qh; ++k) {
+      cphi[k] = double(std::cos(2.0L * pi * k / p.q_phi));
+      const bool single = (k == 0) || (2 * k == p.q_phi);
+      omega[k] = (single ? 1.0 : 2.0) / p.q_phi;
+    }
+    sth.resize(t1.qx);
+    for (int j = 0; j < t1.qx; ++j) sth[j] = std::sqrt(1.0 - t1.xi[j] * t1.xi[j]);
+  }
+  int Q() const { return t1.qp * t1.qx * qh; }
+  double vx(int j, int k) const { return sth[j] * cphi[k]; }
+  double vz(int j) const { return t1.xi[j]; }
+};
+
+struct Macro2 {
+  double e, vx, vz, gamma, ux, uz, n, T;
+};
+
+// Moments of one cell (s-major layout with `cells` values per point row).
+void plane_moments(const PlaneTables& pt, const double* F, int64_t cells, int64_t c, double m[9]) {
+  for (int a = 0; a < 9; ++a) m[a] = 0.0;
+  const Tables& tb = pt.t1;
+  const double t3 = tb.T0 * tb.T0 * tb.T0, t4 = t3 * tb.T0;
+  for (int i = 0; i < tb.qp; ++i)
+    for (int j = 0; j < tb.qx; ++j)
+      for (int k = 0; k < pt.qh; ++k) {
+        const int s = (i * tb.qx + j) * pt.qh + k;
+        const double f = tb.wp[i] * tb.wxi[j] * pt.omega[k] * F[s * cells + c];
+        const double vx = pt.vx(j, k), vz = pt.vz(j), p = tb.p[i];
+        m[0] += t3 * p * f;
+        m[1] += t3 * p * vx * f;
+        m[2] += t3 * p * vz * f;
+        m[3] += t4 * p * p * f;
+        m[4] += t4 * p * p * vx * f;
+        m[5] += t4 * p * p * vz * f;
+        m[6] += t4 * p * p * vx * vx * f;
+        m[7] += t4 * p * p * vx * vz * f;
+        m[8] += t4 * p * p * vz * vz * f;
+      }
+}
+
+// Landau frame of the 9 moments by the power method on T^mu_nu (extended
+// precision; converged when a step changes v by less than 1e-19).
+Macro2 landau2(const double m[9]) {
+  typedef long double E;
+  const E N0 = m[0], Nx = m[1], Nz = m[2], T00 = m[3], T0x = m[4], T0z = m[5], Txx = m[6], Txz = m[7],
+          Tzz = m[8];
+  E vx = 0, vz = 0;
+  for (int it = 0; it < 1000000; ++it) {
+    const E e = T00 - T0x * vx - T0z * vz;
+    const E nx_ = (T0x - Txx * vx - Txz * vz) / e, nz_ = (T0z - Txz * vx - Tzz * vz) / e;
+    const E d = std::fabs(nx_ - vx) + std::fabs(nz_ - vz);
+    vx = nx_;
+    vz = nz_;
+    if (!(d > 1e-19L)) break;
+  }
+  Macro2 M;
+  const E e = T00 - T0x * vx - T0z * vz;
+  const E gamma = 1 / std::sqrt(1 - vx * vx - vz * vz);
+  M.e = double(e);
+  M.vx = double(vx);
+  M.vz = double(vz);
+  M.gamma = double(gamma);
+  M.ux = double(gamma * vx);
+  M.uz = double(gamma * vz);
+  M.n = double(gamma * (N0 - vx * Nx - vz * Nz));
+  M.T = double(e / (3 * gamma * (N0 - vx * Nx - vz * Nz)));
+  return M;
+}
+
+// Truncated equilibrium at every point of the plane's quadrature.
+void plane_feq_nodes(const PlaneTables& pt, double n, double T, double ux, double uz, double* Feq) {
+  const Tables& tb = pt.t1;
+  const double ua = std::sqrt(ux * ux + uz * uz), gamma = std::sqrt(1.0 + ua * ua);
+  const double hx = ua > 0.0 ? ux / ua : 0.0, hz = ua > 0.0 ? uz / ua : 1.0;
+  std::vector<double> C((tb.nv + 1) * (tb.np + 1));
+  feq_coefficients(tb, n, T, gamma, ua, C.data());
+  for (int i = 0; i < tb.qp; ++i)
+    for (int j = 0; j < tb.qx; ++j)
+      for (int k = 0; k < pt.qh; ++k) {
+        const double c = pt.vx(j, k) * hx + pt.vz(j) * hz;
+        double acc = 0.0;
+        for (int l = 0; l <= tb.np; ++l)
+          for (int kk = 0; kk <= tb.nv; ++kk)
+            acc += (2.0 * kk + 1.0) / 2.0 / (l + 1.0) * legendre_P(kk, c) * tb.Ll[i * (tb.np + 1) + l] *
+                   C[kk * (tb.np + 1) + l];
+        Feq[(i * tb.qx + j) * pt.qh + k] = acc;
+      }
+}
+
+// WENO value at face y+1/2 of a strided line of n values (outflow clamps),
+// upwinded by the sign of the velocity component.
+double face_value_line(const double* base, int64_t n, int64_t stride, int64_t y, double vel, double eps) {
+  auto g = [&](int64_t q) { return base[clampx(q, n) * stride]; };
+  if (vel >= 0.0) return weno5(g(y - 2), g(y - 1), g(y), g(y + 1), g(y + 2), eps);
+  return weno5(g(y + 3), g(y + 2), g(y + 1), g(y), g(y - 1), eps);
+}
+
+void plane_rhs(const PlaneTables& pt, const oracle_plane& pl, const double* F, double* out) {
+  const int64_t nx = pl.nx, nz = pl.nz, cells = nx * nz;
+  const double dx = (pl.x_max - pl.x_min) / pl.nx, dz = (pl.z_max - pl.z_min) / pl.nz;
+  const double tau_inv = 1.0 / pl.tau;
+  const Tables& tb = pt.t1;
+  const int Q = pt.Q();
+#pragma omp parallel
+  {
+    std::vector<double> feq(Q);
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < cells; ++c) {
+      const int64_t z = c / nx, x = c % nx;
+      double m[9];
+      plane_moments(pt, F, cells, c, m);
+      const Macro2 M = landau2(m);
+      plane_feq_nodes(pt, M.n, M.T, M.ux, M.uz, feq.data());
+      for (int i = 0; i < tb.qp; ++i)
+        for (int j = 0; j < tb.qx; ++j)
+          for (int k = 0; k < pt.qh; ++k) {
+            const int s = (i * tb.qx + j) * pt.qh + k;
+            const double vx = pt.vx(j, k), vz = pt.vz(j);
+            const double* plane = F + s * cells;
+            const double hxr = face_value_line(plane + z * nx, nx, 1, x, vx, pl.weno_eps);
+            const double hxl = face_value_line(plane + z * nx, nx, 1, x - 1, vx, pl.weno_eps);
+            const double hzr = face_value_line(plane + x, nz, nx, z, vz, pl.weno_eps);
+            const double hzl = face_value_line(plane + x, nz, nx, z - 1, vz, pl.weno_eps);
+            const double adv = -vx / dx * (hxr - hxl) - vz / dz * (hzr - hzl);
+            const double rate = (M.gamma - vx * M.ux - vz * M.uz) * tau_inv;
+            out[s * cells + c] = adv - rate * (plane[c] - feq[s]);
+          }
+    }
+  }
+}
+
+void plane_rk3_step(const PlaneTables& pt, const oracle_plane& pl, double* F, double* F1, double* F2, double* L) {
+  const int64_t N = int64_t(pt.Q()) * pl.nx * pl.nz;
+  const double dt = pl.dt;
+  plane_rhs(pt, pl, F, L);
+  for (int64_t a = 0; a < N; ++a) F1[a] = F[a] + dt * L[a];
+  plane_rhs(pt, pl, F1, L);
+  for (int64_t a = 0; a < N; ++a) F2[a] = 0.75 * F[a] + 0.25 * (F1[a] + dt * L[a]);
+  plane_rhs(pt, pl, F2, L);
+  for (int64_t a = 0; a < N; ++a) F[a] = (1.0 / 3.0) * F[a] + (2.0 / 3.0) * (F2[a] + dt * L[a]);
+}
+
+bool plane_valid(const oracle_plane* p) {
+  return p && p->nx >= 1 && p->nz >= 1 && p->q_xi >= 1 && p->q_phi >= 1 && p->q_p >= 1 && p->n_v >= 0 &&
+         p->n_p >= 0 && p->tau > 0 && p->dt > 0 && p->T0 > 0 && p->x_max > p->x_min && p->z_max > p->z_min;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Azimuthal rule of the plane: cos(phi_k) and omega_k of the evolved nodes.
+int oracle_plane_tables(const oracle_plane* p, double* cphi, double* omega) {
+  if (!plane_valid(p)) return -1;
+  PlaneTables pt(*p);
+  for (int k = 0; k < pt.qh; ++k) {
+    cphi[k] = pt.cphi[k];
+    omega[k] = pt.omega[k];
+  }
+  return 0;
+}
+
+// Landau frame of (N0, Nx, Nz, T00, T0x, T0z, Txx, Txz, Tzz) -> e, vx, vz, gamma, n, T.
+int oracle_landau2d(const double* m, double* out) {
+  const Macro2 M = landau2(m);
+  const double r[6] = {M.e, M.vx, M.vz, M.gamma, M.n, M.T};
+  for (int a = 0; a < 6; ++a) out[a] = r[a];
+  return 0;
+}
+
+int oracle_plane_feq_nodes(const oracle_plane* p, double n, double T, double ux, double uz, double* F) {
+  if (!plane_valid(p)) return -1;
+  PlaneTables pt(*p);
+  plane_feq_nodes(pt, n, T, ux, uz, F);
+  return 0;
+}
+
+// Initial distribution from per-cell states fields[4][nz][nx] = P, n, u^x, u^z.
+int oracle_plane_init(const oracle_plane* p, const double* fields, double* F) {
+  if (!plane_valid(p)) return -1;
+  PlaneTables pt(*p);
+  const int64_t cells = int64_t(p->nx) * p->nz;
+  std::vector<double> feq(pt.Q());
+  for (int64_t c = 0; c < cells; ++c) {
+    const double P = fields[c], n = fields[cells + c], ux = fields[2 * cells + c], uz = fields[3 * cells + c];
+    plane_feq_nodes(pt, n, P / n, ux, uz, feq.data());
+    for (int s = 0; s < pt.Q(); ++s) F[s * cells + c] = feq[s];
+  }
+  return 0;
+}
+
+int oracle_plane_step(const oracle_plane* p, double* F, int64_t nsteps) {
+  if (!plane_valid(p) || nsteps < 0) return -1;
+  PlaneTables pt(*p);
+  const size_t N = size_t(pt.Q()) * p->nx * p->nz;
+  std::vector<double> F1(N), F2(N), L(N);
+  for (int64_t n = 0; n < nsteps; ++n) plane_rk3_step(pt, *p, F, F1.data(), F2.data(), L.data());
+  return 0;
+}
+
+int oracle_plane_rhs(const oracle_plane* p, const double* F, double* out) {
+  if (!plane_valid(p)) return -1;
+  PlaneTables pt(*p);
+  plane_rhs(pt, *p, F, out);
+  return 0;
+}
+
+// Fields per cell [14][nz][nx]: the 9 moments, e, n, v_x, v_z, T.
+int oracle_plane_fields(const oracle_plane* p, const double* F, double* out) {
+  if (!plane_valid(p)) return -1;
+  PlaneTables pt(*p);
+  const int64_t cells = int64_t(p->nx) * p->nz;
+  for (int64_t c = 0; c < cells; ++c) {
+    double m[9];
+    plane_moments(pt, F, cells, c, m);
+    const Macro2 M = landau2(m);
+    for (int a = 0; a < 9; ++a) out[a * cells + c] = m[a];
+    out[9 * cells + c] = M.e;
+    out[10 * cells + c] = M.n;
+    out[11 * cells + c] = M.vx;
+    out[12 * cells + c] = M.vz;
+    out[13 * cells + c] = M.T;
+  }
+  return 0;
+}
+
+}  // extern "C"
