@@ -236,6 +236,80 @@ rlb_status rlb_device_copy(void* dst, const void* src, size_t bytes, void* hip_s
 const char* rlb_status_string(rlb_status st);
 const char* rlb_last_error(const rlb_lattice* lat);
 
+/*
+ * Multi-dimensional model on an (x, z) plane: eq. Boltz_gen with the particle
+ * velocity v = (sin(theta) cos(phi), sin(theta) sin(phi), cos(theta)) resolved
+ * in the plane, for data independent of y, on the full product quadrature of
+ * the section "Discretization of the momentum space": q_p Gauss-Laguerre x
+ * q_xi Gauss-Legendre x the q_phi-node trapezoid rule of eq. azimuthInt
+ * (phi_k = 2 pi k / q_phi).  With u^y = 0 the nodes phi and -phi carry equal
+ * values, so q_p * q_xi * (q_phi/2 + 1) points are evolved per cell.  The
+ * Landau frame is the timelike eigenvector of T^mu_nu; the truncated
+ * equilibrium (eq. feqtrunc) is the Legendre series of order n_v in v . u/|u|.
+ * Cells are cell-centred on [x_min, x_max] x [z_min, z_max]; every edge is an
+ * outflow (zero-gradient) boundary.
+ *
+ *   nx, nz     -- cells, 8 <= each, nx * nz <= 2^26;
+ *   q_xi, q_phi, q_p, n_v, n_p -- as for a tube (n_v <= 7), plus
+ *                 n_v + 3 <= q_phi <= 64 (the azimuthal rule integrates the
+ *                 moments of the equilibrium exactly);
+ *   tau, T0, weno_eps -- as for a tube;
+ *   dt         -- > 0: explicit; 0: min(cfl / (1/dx + 1/dz), dt_tau_max tau).
+ *                 dt (1/dx + 1/dz) <= 1.5 and dt <= 2.5 tau are required.
+ *
+ * State layout (rlb_plane_layout): F[s][z][ldx], s = (i q_xi + j) (q_phi/2+1)
+ * + k, precision of the plane, ldx >= nx.  Ownership as for a lattice: the
+ * caller owns the workspace (rlb_plane_workspace_size bytes, 256-byte aligned)
+ * and the stream; calls are asynchronous on that stream except where noted.
+ */
+typedef struct {
+  int32_t nx, nz;
+  int32_t q_xi, q_phi, q_p;
+  int32_t n_v, n_p;
+  int32_t reserved0;
+  double x_min, x_max, z_min, z_max;
+  double tau;
+  double cfl;
+  double dt_tau_max;
+  double dt;
+  double T0;
+  double weno_eps;
+} rlb_plane_desc;
+
+typedef struct rlb_plane rlb_plane;
+
+/* Defaults: 64 x 64 cells on [-0.5, 0.5]^2, q_xi 8, q_phi 8, q_p 3, n_v 5,
+ * n_p 2, tau 1e-2, cfl 0.5, dt_tau_max 0.5, T0 1, weno_eps 1e-6. */
+rlb_status rlb_plane_defaults(rlb_plane_desc* desc);
+/* Validates the descriptor and builds the host tables; no device work. */
+rlb_status rlb_plane_create(const rlb_plane_desc* desc, rlb_precision prec, rlb_plane** out);
+rlb_status rlb_plane_destroy(rlb_plane* pl);
+rlb_status rlb_plane_workspace_size(const rlb_plane* pl, size_t* bytes);
+/* Binds the caller's device workspace and stream, clears it and uploads the
+ * tables (synchronizes). */
+rlb_status rlb_plane_bind(rlb_plane* pl, void* workspace, size_t bytes, void* hip_stream);
+/* Initial state: every cell takes the truncated equilibrium of its state
+ * fields_device[4][nz][nx] (FP64 device memory: P, n, u^x, u^z; P, n > 0),
+ * which must stay valid until the stream reaches this call.  Time restarts at
+ * 0 and the sticky flag is cleared. */
+rlb_status rlb_plane_set_initial_fields(rlb_plane* pl, const double* fields_device);
+/* nsteps SSP-RK3 steps (three stage launches each). */
+rlb_status rlb_plane_step(rlb_plane* pl, int64_t nsteps);
+/* Fields [14][nz][nx] (FP64 device memory): N0, Nx, Nz, T00, T0x, T0z, Txx,
+ * Txz, Tzz, e, n, v_x, v_z, T of the current state.  A non-physical cell sets
+ * the sticky flag. */
+rlb_status rlb_plane_fields(rlb_plane* pl, double* out_device);
+rlb_status rlb_plane_layout(const rlb_plane* pl, int64_t* state_elems, int64_t* ldx);
+/* Copy the current state out of / into the workspace (device buffers of
+ * state_elems elements); setting a state recomputes its records. */
+rlb_status rlb_plane_get_state(rlb_plane* pl, void* dst_device);
+rlb_status rlb_plane_set_state(rlb_plane* pl, const void* src_device);
+/* Time step, elapsed time and evolved points per cell (host values). */
+rlb_status rlb_plane_info(const rlb_plane* pl, double* dt, double* time, int32_t* Q);
+/* Synchronizes and reports the sticky non-physical flag. */
+rlb_status rlb_plane_check(rlb_plane* pl);
+const char* rlb_plane_last_error(const rlb_plane* pl);
+
 #ifdef __cplusplus
 }
 #endif

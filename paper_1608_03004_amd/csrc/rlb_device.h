@@ -72,6 +72,25 @@ __device__ inline bool left_of_split(double z_min, double dz, int x) {
 }
 __device__ inline bool left_of_split(const TubeDev& tb, int x) { return left_of_split(tb.z_min, tb.dz, x); }
 
+// XCD-aware work distribution.  Workgroups are dispatched round-robin over the
+// 8 XCDs (workgroup b runs on XCD b % 8), and each XCD has its own L2.  The
+// work list keeps a tube's tiles in ascending order; handing each XCD runs of
+// kXcdRun consecutive items puts neighbouring tiles -- which read each other's
+// 3-cell halos -- on the same L2, while the interleaving of runs keeps the
+// cost balanced when the list is sorted by cost (batched tubes).  v is the
+// workgroup's virtual index (blockIdx.x + k * gridDim.x with gridDim.x a
+// multiple of 8, or plain blockIdx.x); the map is a bijection on [0, n): items
+// past the last whole super-block of 8 * kXcdRun are taken in order.
+constexpr int kXcds = 8;
+constexpr int kXcdRun = 16;
+__device__ inline int xcd_item(int v, int n) {
+  constexpr int S = kXcds * kXcdRun;
+  const int n_full = (n / S) * S;
+  if (v >= n_full) return v;
+  const int x = v % kXcds, k = v / kXcds;
+  return (k / kXcdRun) * S + x * kXcdRun + (k % kXcdRun);
+}
+
 struct Macro {
   double e, v, gamma, u, n, T;
   bool ok;

@@ -178,6 +178,48 @@ hipError_t launch_feq(int prec_fp32, const LaunchShape& ls, const void* args, hi
 hipError_t launch_combine(const TubeDev* tubes, const WorkItem* items, int nitems, int tile, const double* itab,
                           const double* part, int part_stride, double* rec_out, hipStream_t stream);
 
+// ---------------------------------------------------------------------------
+// Multi-dimensional model on an (x, z) plane (rlb_plane.hip, rlb_plane_api.cpp)
+// ---------------------------------------------------------------------------
+// Point s = (i * qx + j) * qh + k: radial node i, polar node j, evolved
+// azimuthal node k = 0 .. qh - 1 (qh = q_phi / 2 + 1; the mirrored nodes
+// q_phi - k carry equal values for data with u^y = 0).  State F[s][z][ldx],
+// records rec[9][z][ldx] (N0, Nx, Nz, T00, T0x, T0z, Txx, Txz, Tzz).
+// Velocity table row per (j, k): v_x, v_z, then the weighted moment factors
+// w, w v_x, w v_z, w v_x^2, w v_x v_z, w v_z^2 with w = w_xi[j] omega[k].
+constexpr int kVStride = 8;
+constexpr int kPlaneTileX = 64, kPlaneTileZ = 4;  // cells per workgroup
+
+struct PlaneDev {
+  int32_t nx, nz, ldx;
+  int32_t qx, qh, qp, nv, np;
+  int64_t plane;  // elements per point plane (nz * ldx)
+  double dx_inv, dz_inv, dt, tau_inv, T0, weno_eps;
+};
+
+template <typename Real>
+struct PlaneArgs {
+  const PlaneDev* pl;
+  int32_t stage;      // 1, 2, 3 (SSP-RK3 stage)
+  int32_t aux_pairs;
+  const Real* vtab;   // [qx * qh][kVStride]
+  const double* itab; // radial rows (kIStride)
+  const Real* aux;    // projection rule (kAuxStride)
+  const Real* fin;
+  const Real* fn;
+  Real* fout;
+  const double* rec_in;
+  double* rec_out;
+  unsigned* flag;
+  const double* init;  // init kernel: per-cell P, n, u^x, u^z [4][nz][nx]
+};
+
+hipError_t launch_plane_stage(int prec_fp32, int qpt, int nvt, const void* args, int grid, hipStream_t stream);
+hipError_t launch_plane_init(int prec_fp32, int qpt, int nvt, const void* args, int grid, hipStream_t stream);
+hipError_t launch_plane_moments(int prec_fp32, const void* args, int grid, hipStream_t stream);
+hipError_t launch_plane_fields(const PlaneDev* pl, int nx, int nz, const double* rec, double* out, unsigned* flag,
+                               hipStream_t stream);
+
 // Adjoint launchers (defined in rlb_adjoint.hip); one tube per call.
 hipError_t launch_adjoint_stage(int prec_fp32, int qpt, int nvt, int nx, int Q, const void* args, hipStream_t stream);
 hipError_t launch_tau_reduce(const TubeDev* tubes, int tube, const double* tau_acc, double* dL_dtau,

@@ -145,3 +145,46 @@ def test_device_tables_match_the_oracle(lib, q_xi, q_p):
 def test_status_strings(lib):
     for st in range(0, -6, -1):
         assert lib.rlb_status_string(st)
+
+
+def _plane_create(lib, spec, prec=rlb.RLB_FP64):
+    h = ctypes.c_void_p()
+    st = lib.rlb_plane_create(ctypes.byref(spec.c()), prec, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(nx=4), rlb.RLB_ERR_INVALID_ARG),
+    (dict(nz=7), rlb.RLB_ERR_INVALID_ARG),
+    (dict(nx=1 << 14, nz=1 << 13), rlb.RLB_ERR_INVALID_ARG),        # more than 2^26 cells
+    (dict(q_phi=7), rlb.RLB_ERR_INVALID_ARG),                       # q_phi < n_v + 3
+    (dict(q_phi=65), rlb.RLB_ERR_INVALID_ARG),
+    (dict(n_v=8), rlb.RLB_ERR_INVALID_ARG),
+    (dict(q_p=9), rlb.RLB_ERR_INVALID_ARG),
+    (dict(tau=0.0), rlb.RLB_ERR_INVALID_ARG),
+    (dict(x_min=0.5, x_max=-0.5), rlb.RLB_ERR_INVALID_ARG),
+    (dict(dt=0.02), rlb.RLB_ERR_UNSTABLE_DT),                       # dt (1/dx + 1/dz) = 2.56
+])
+def test_invalid_plane_descriptors_are_rejected(lib, bad, status):
+    st, h = _plane_create(lib, rlb.PlaneSpec(**bad))
+    assert st == status and not h.value
+    assert lib.rlb_plane_last_error(None)
+
+
+def test_valid_plane_create_and_host_queries(lib):
+    d = rlb.PlaneDesc()
+    assert lib.rlb_plane_defaults(ctypes.byref(d)) == 0
+    assert (d.nx, d.nz, d.q_xi, d.q_phi, d.q_p, d.n_v, d.n_p) == (64, 64, 8, 8, 3, 5, 2)
+    spec = rlb.PlaneSpec(nx=70, nz=13, q_phi=9, tau=1.0)
+    st, h = _plane_create(lib, spec)
+    assert st == 0, lib.rlb_plane_last_error(None)
+    n, ld = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.rlb_plane_layout(h, ctypes.byref(n), ctypes.byref(ld)) == 0
+    assert ld.value == 128 and n.value == 3 * 8 * 5 * 13 * 128
+    size = ctypes.c_size_t()
+    assert lib.rlb_plane_workspace_size(h, ctypes.byref(size)) == 0 and size.value >= 3 * n.value * 8
+    dt, t, Q = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    assert lib.rlb_plane_info(h, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(Q)) == 0
+    assert Q.value == 120 and abs(dt.value - 0.5 / (70 + 13)) < 1e-18
+    assert lib.rlb_plane_step(h, 1) == rlb.RLB_ERR_STATE
+    assert lib.rlb_plane_destroy(h) == 0
