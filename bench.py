@@ -16,6 +16,8 @@ whole tube.  Beside it, on the same line:
   ballistic   the 2^22-cell, Q = 256 x 4 tube at tau = 1e3 (FP32);
   high        the headline tube with the high-order equilibrium (N_v = 63),
               FP32 and FP64, with the matrix-core roofline of its pre-pass;
+  plane       the multi-dimensional model on a 1024 x 1024 plane (Q = 120),
+              FP32 and FP64;
   roofline    of the stage kernel: algorithmic bytes per launch over its mean
               duration, timed with HIP events on the launch stream;
   cpu_baseline the CPU FP64 oracle on a bounded sample of the headline tube.
@@ -59,26 +61,34 @@ def timed_steps(lat, steps):
     return wall, start.elapsed_time(stop) * 1e-3
 
 
-def kernel_source_sha1():
+KERNEL_SOURCES = {"stage_kernel": "rlb_kernels.hip", "feq_kernel": "rlb_feq.hip", "plane_stage_kernel": "rlb_plane.hip"}
+TRAFFIC_FILES = {"stage_kernel": "stage_kernel_traffic.json", "feq_kernel": "feq_kernel_traffic.json",
+                 "plane_stage_kernel": "plane_stage_kernel_traffic.json"}
+
+
+def kernel_source_sha1(kernel="stage_kernel"):
+    """SHA-1 of the sources a kernel is built from (its own file and the two
+    shared headers)."""
     import hashlib
     h = hashlib.sha1()
-    for f in ("rlb_kernels.hip", "rlb_device.h", "rlb_internal.h"):
+    for f in (KERNEL_SOURCES[kernel], "rlb_device.h", "rlb_internal.h"):
         with open(os.path.join(ROOT, "paper_1608_03004_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(precision):
-    """HBM bytes per stage launch of the headline tube from the committed
-    rocprofv3 FETCH_SIZE/WRITE_SIZE runs (calibrated on the copy kernel), or
-    None when the kernel sources changed since those counters were taken."""
-    path = os.path.join(ROOT, "profiles", "stage_kernel_traffic.json")
+def measured_traffic(precision, kernel="stage_kernel"):
+    """HBM bytes per launch of a kernel on its benchmark workload from the
+    committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs (calibrated on the copy
+    kernel), or None when the kernel's sources changed since those counters
+    were taken."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[kernel])
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha1") != kernel_source_sha1() or precision not in t:
+    if t.get("kernel_source_sha1") != kernel_source_sha1(kernel) or precision not in t:
         return None
     return int(t[precision]["traffic_bytes_per_launch"])
 
@@ -252,13 +262,75 @@ def leg_high_order(precision, steps, warmup=2, reps=10):
     res = dict(value=tube.nx * tube.Q * steps / wall, unit="cell*quad-point updates/s",
                ms_per_step=1e3 * wall / steps, steps=steps,
                roofline=dict(bound="mfma", achieved=round(flops / feq_s / 1e12, 2), peak=MFMA_F64_PEAK_TFS,
-                             unit="TFLOP/s", frac=round(flops / feq_s / 1e12 / MFMA_F64_PEAK_TFS, 4), traffic=None,
+                             unit="TFLOP/s", frac=round(flops / feq_s / 1e12 / MFMA_F64_PEAK_TFS, 4),
+                             traffic=measured_traffic(precision, "feq_kernel"),
                              kernel="feq_kernel", flops_per_launch=flops, launch_us=round(feq_s * 1e6, 2)),
                stage_roofline=dict(bound="hbm", achieved=round(stage_bytes / stage_s / 1e9, 1), peak=HBM_PEAK_GBS,
                                    unit="GB/s", frac=round(stage_bytes / stage_s / 1e9 / HBM_PEAK_GBS, 4),
                                    bytes_per_launch=int(stage_bytes), launch_us=round(stage_s * 1e6, 2)),
                workload=f"sod_large_high_order: N_x=2^20, Q=64x4, N_v=63, N_p=2, tau=1e-2, {precision.upper()}")
     del lat, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def plane_quadrants(nx, nz):
+    """Per-cell (P, n, u^x, u^z) of a 2D Riemann problem: four constant states
+    meeting at the centre of [-0.5, 0.5]^2."""
+    import numpy as np
+    x = -0.5 + (np.arange(nx) + 0.5) / nx
+    z = -0.5 + (np.arange(nz) + 0.5) / nz
+    X, Z = np.meshgrid(x, z)
+    states = {(0, 0): (1.0, 1.0, 0.0, 0.0), (1, 0): (0.3, 0.5, 0.2, 0.0),
+              (0, 1): (0.4, 0.6, 0.0, -0.3), (1, 1): (0.1, 0.125, 0.1, 0.1)}
+    f = np.zeros((4, nz, nx))
+    for (a, b), st in states.items():
+        m = ((X >= 0) == bool(a)) & ((Z >= 0) == bool(b))
+        for c in range(4):
+            f[c][m] = st[c]
+    return f
+
+
+def plane_step_bytes(spec, rsize):
+    """Algorithmic HBM bytes of one plane step: 8 accesses per point (as for a
+    tube) and per cell and stage the nine FP64 records read and written."""
+    return 8 * spec.nx * spec.nz * spec.Q * rsize + 3 * 144 * spec.nx * spec.nz
+
+
+def leg_plane(precision, steps, warmup=2):
+    """The multi-dimensional model: a 1024 x 1024 plane, Q = 3 x 8 x 5 evolved
+    points (Q_phi = 8), a 2D Riemann problem."""
+    import torch
+    from paper_1608_03004_amd import Plane, PlaneSpec
+    spec = PlaneSpec(nx=1024, nz=1024, q_xi=8, q_phi=8, q_p=3, tau=1e-2)
+    gp = Plane(spec, precision=precision)
+    gp.set_initial_fields(plane_quadrants(spec.nx, spec.nz))
+    gp.step(warmup)
+    gp.check()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(gp.stream)
+    gp.step(steps)
+    stop.record(gp.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gp.check()
+    ev = start.elapsed_time(stop) * 1e-3
+    rsize = 4 if precision == "fp32" else 8
+    launch_s = ev / (3 * steps)
+    bytes_launch = plane_step_bytes(spec, rsize) / 3
+    pts = spec.nx * spec.nz * spec.Q
+    res = dict(value=pts * steps / wall, unit="cell*quad-point updates/s", ms_per_step=1e3 * wall / steps,
+               steps=steps,
+               roofline=dict(bound="hbm", achieved=round(bytes_launch / launch_s / 1e9, 1), peak=HBM_PEAK_GBS,
+                             unit="GB/s", frac=round(bytes_launch / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                             traffic=measured_traffic(precision, "plane_stage_kernel"), kernel="plane_stage_kernel",
+                             bytes_per_launch=int(bytes_launch),
+                             launch_us=round(launch_s * 1e6, 2)),
+               workload=f"plane_quadrants: 1024 x 1024 cells, Q = 3 x 8 x (8/2+1) = 120, N_v = 5, tau = 1e-2, "
+                        f"2D Riemann problem, {precision.upper()}")
+    del gp
     torch.cuda.empty_cache()
     return res
 
@@ -316,9 +388,10 @@ def main():
     ap.add_argument("--tile", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"),
                     help="form of the headline tube (fp64 is for profiling runs; the headline is fp32)")
-    ap.add_argument("--legs", default="fp64,batched,adjoint,ballistic,high,copy,cpu",
-                    help="comma-separated extra legs (fp64, batched, adjoint, ballistic, high, copy, cpu) "
-                         "or 'none'")
+    ap.add_argument("--legs", default="fp64,batched,adjoint,ballistic,high,plane,copy,cpu",
+                    help="comma-separated extra legs (fp64, batched, adjoint, ballistic, high, plane, copy, "
+                         "cpu) or 'none'")
+    ap.add_argument("--plane-steps", type=int, default=20)
     ap.add_argument("--high-steps", type=int, default=20)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--ballistic-steps", type=int, default=20)
@@ -369,6 +442,8 @@ def main():
     if "high" in legs:
         line["high_order"] = dict(fp32=leg_high_order("fp32", args.high_steps),
                                   fp64=leg_high_order("fp64", args.high_steps))
+    if "plane" in legs:
+        line["plane"] = dict(fp32=leg_plane("fp32", args.plane_steps), fp64=leg_plane("fp64", args.plane_steps))
     if "copy" in legs:
         line["copy"] = leg_copy()
     if "cpu" in legs:
