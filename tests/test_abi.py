@@ -106,6 +106,7 @@ def test_high_order_tubes_create_without_adjoint(lib):
     lib.rlb_destroy(h)
     st, h = _create(lib, high[:1])
     assert st == 0, lib.rlb_last_error(None)
+    assert lib.rlb_equilibrium(h, None) == rlb.RLB_ERR_STATE  # no workspace bound yet
     size = ctypes.c_size_t()
     lib.rlb_workspace_size(h, ctypes.byref(size))
     assert size.value >= base.value + 256 * 320 * 8

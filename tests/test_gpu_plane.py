@@ -157,3 +157,21 @@ def test_plane_full_size_window(torch_cuda):
     errs = _fields_err(full, ref)
     print("[plane 1024^2 fp32 window] " + " ".join(f"{k}:{v:.1e}" for k, v in errs.items()), flush=True)
     assert max(errs.values()) < 1e-5, errs
+
+
+def test_plane_nonphysical_state_raises_sticky_flag(torch_cuda):
+    from paper_1608_03004_amd import Plane, RLBError
+    spec, opl = _specs(dict(nx=16, nz=16, q_xi=6, q_phi=8, q_p=3, tau=1e-2))
+    gp = Plane(spec)
+    f = _blob(opl)
+    gp.set_initial_fields(f)
+    bad = gp.get_state().clone()
+    bad.mul_(-1.0)  # a negative distribution: e < 0 in every cell
+    gp.set_state(bad)
+    gp.step(1)
+    with pytest.raises(RLBError) as ei:
+        gp.check()
+    assert ei.value.status == -2
+    gp.set_initial_fields(f)  # a fresh initial state clears the flag
+    gp.step(1)
+    gp.check()
