@@ -243,6 +243,7 @@ def leg_high_order(precision, steps, warmup=2, reps=10):
     lat.check()
     wall, ev = timed_steps(lat, steps)
     lat.check()
+    fields = lat.moments(0)
     # the pre-pass alone on the lattice's stream (same launch as inside a stage)
     out = lat.new_state()
     lat.equilibrium(out)
@@ -271,7 +272,7 @@ def leg_high_order(precision, steps, warmup=2, reps=10):
                workload=f"sod_large_high_order: N_x=2^20, Q=64x4, N_v=63, N_p=2, tau=1e-2, {precision.upper()}")
     del lat, out
     torch.cuda.empty_cache()
-    return res
+    return res, fields
 
 
 def plane_quadrants(nx, nz):
@@ -316,6 +317,7 @@ def leg_plane(precision, steps, warmup=2):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gp.check()
+    fields = gp.moments()
     ev = start.elapsed_time(stop) * 1e-3
     rsize = 4 if precision == "fp32" else 8
     launch_s = ev / (3 * steps)
@@ -332,7 +334,20 @@ def leg_plane(precision, steps, warmup=2):
                         f"2D Riemann problem, {precision.upper()}")
     del gp
     torch.cuda.empty_cache()
-    return res
+    return res, fields
+
+
+def plane_error_table(f32, f64):
+    """Max and L2 relative errors (normwise per field) of the FP32 plane
+    against the FP64 plane after the same steps."""
+    import numpy as np
+    names = dict(e=9, vx=11, vz=12, T00=3, T0x=4, T0z=5, Txx=6, Txz=7, Tzz=8, N0=0, n=10)
+    out = {}
+    for name, k in names.items():
+        d = f32[k] - f64[k]
+        s = max(np.abs(f64[k]).max(), 1e-300)
+        out[name] = dict(max=float(np.abs(d).max() / s), l2=float(np.sqrt(np.mean(d * d)) / s))
+    return out
 
 
 def leg_copy(nbytes=1 << 30, reps=5):
@@ -440,10 +455,15 @@ def main():
     if "ballistic" in legs:
         line["ballistic"] = leg_ballistic(args.ballistic_steps)
     if "high" in legs:
-        line["high_order"] = dict(fp32=leg_high_order("fp32", args.high_steps),
-                                  fp64=leg_high_order("fp64", args.high_steps))
+        h32, hf32 = leg_high_order("fp32", args.high_steps)
+        h64, hf64 = leg_high_order("fp64", args.high_steps)
+        line["high_order"] = dict(fp32=h32, fp64=h64, fp32_vs_fp64_error=dict(
+            after_steps=args.high_steps + 2, fields=error_table(hf32, hf64)))
     if "plane" in legs:
-        line["plane"] = dict(fp32=leg_plane("fp32", args.plane_steps), fp64=leg_plane("fp64", args.plane_steps))
+        p32, pf32 = leg_plane("fp32", args.plane_steps)
+        p64, pf64 = leg_plane("fp64", args.plane_steps)
+        line["plane"] = dict(fp32=p32, fp64=p64, fp32_vs_fp64_error=dict(
+            after_steps=args.plane_steps + 2, fields=plane_error_table(pf32, pf64)))
     if "copy" in legs:
         line["copy"] = leg_copy()
     if "cpu" in legs:
