@@ -95,6 +95,15 @@ struct rlb_lattice {
 
 namespace {
 
+// Device-to-device copy of a state: the library's 16-byte vector copy kernel
+// when both ends are 16-byte aligned, the runtime's copy otherwise (caller
+// buffers may be views at any element offset).
+hipError_t state_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16) == 0)
+    return launch_copy(dst, src, bytes, s);
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+
 rlb_status fail(rlb_lattice* L, rlb_status st, const std::string& msg) {
   if (L) L->err = msg; else g_create_error = msg;
   return st;
@@ -857,7 +866,7 @@ rlb_status rlb_get_state(rlb_lattice* L, void* dst) {
   rlb_status st = need_ready(L, true);
   if (st != RLB_OK) return st;
   if (!dst) return fail(L, RLB_ERR_INVALID_ARG, "dst is NULL");
-  hipError_t e = launch_copy(dst, L->ws + L->off_F[0], L->state_elems * L->rsize, L->stream);
+  hipError_t e = state_copy(dst, L->ws + L->off_F[0], L->state_elems * L->rsize, L->stream);
   if (e != hipSuccess) return hip_fail(L, e, "state copy");
   return RLB_OK;
 }
@@ -881,7 +890,7 @@ rlb_status rlb_set_state(rlb_lattice* L, const void* src) {
   rlb_status st = need_ready(L, false);
   if (st != RLB_OK) return st;
   if (!src) return fail(L, RLB_ERR_INVALID_ARG, "src is NULL");
-  hipError_t e = launch_copy(L->ws + L->off_F[0], src, L->state_elems * L->rsize, L->stream);
+  hipError_t e = state_copy(L->ws + L->off_F[0], src, L->state_elems * L->rsize, L->stream);
   if (e != hipSuccess) return hip_fail(L, e, "state copy");
   const bool fp32 = L->prec == RLB_FP32;
   e = launch_moments(fp32 ? 1 : 0, L->dev<TubeDev>(L->off_tubes), L->dev<WorkItem>(L->off_items),
@@ -1083,7 +1092,7 @@ rlb_status rlb_adjoint_segment(rlb_lattice* L, const void* state0, int32_t nstep
   auto F = [&](int k, int s) { return static_cast<void*>(base + size_t(k) * ss.bytes + ss.F[s]); };
   auto R = [&](int k, int s) { return reinterpret_cast<double*>(base + size_t(k) * ss.bytes + ss.R[s]); };
   // forward: f^n, f1, f2 of every step of the segment and their records
-  hipError_t e = launch_copy(F(0, 0), state0, L->state_elems * L->rsize, L->stream);
+  hipError_t e = state_copy(F(0, 0), state0, L->state_elems * L->rsize, L->stream);
   if (e != hipSuccess) return hip_fail(L, e, "state copy");
   if ((st = moments_of(L, F(0, 0), R(0, 0))) != RLB_OK) return st;
   for (int k = 0; k < nsteps; ++k) {

@@ -19,11 +19,14 @@
 // RK combination, store, and the nine moments of the output.
 //
 // Work decomposition: one lane per cell, workgroups of 64 x 4 cells (x
-// contiguous in memory).  A lane reads its 7-value x line and 6 more values of
-// its z line for every point (outflow clamps at the edges); neighbouring lanes
-// and waves hit the same lines in L1.  Tiles are ordered z-fastest within an
-// x column and handed to the XCDs in runs, so the z halos of a tile come from
-// the same L2.
+// contiguous in memory).  For every point the workgroup stages the cells of
+// its tile and a 3-cell halo on each side (outflow clamps applied at load
+// time) in LDS, the next point's values already in flight in registers; each
+// lane computes the WENO value of its own left x face and lower z face (the
+// tile's last faces by a few extra lanes), shares them through LDS and forms
+// the update from its two x and two z faces.  Two barriers per point, double
+// buffered.  Tiles are ordered z-fastest within an x column and handed to the
+// XCDs in runs, so the z halos of a tile come from the same L2.
 #include <hip/hip_runtime.h>
 
 #include "rlb_device.h"
@@ -131,8 +134,17 @@ __device__ inline void plane_tile(int v, int nxt, int nzt, int& xt, int& zt) {
   zt = item % nzt;
 }
 
+// LDS tile of one point: rows z0-3 .. z0+6, columns x0-3 .. x0+66 (outflow
+// clamps applied at load time), padded to kTileLd columns.
+constexpr int kTileRows = kPlaneTileZ + 6, kTileCols = kPlaneTileX + 6, kTileLd = kTileCols + 2;
+constexpr int kTileElems = kTileRows * kTileCols;
+constexpr int kTileLoads = (kTileElems + 255) / 256;  // per lane
+
 template <typename Real, int QPT, int NVT, bool HAS_FN>
 __global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
+  __shared__ Real tile[2][kTileRows][kTileLd];
+  __shared__ Real fxs[2][kPlaneTileZ][kPlaneTileX + 1];  // x faces: left face of column q
+  __shared__ Real fzs[2][kPlaneTileZ + 1][kPlaneTileX];  // z faces: lower face of row r
   const cptr<PlaneDev> P = as_const(a.pl);
   const int nx = P->nx, nz = P->nz, ldx = P->ldx, qx = P->qx, qh = P->qh, qp = P->qp;
   const int64_t plane = P->plane;
@@ -144,20 +156,24 @@ __global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
   const Real cs = stage == 1 ? Real(1) : (stage == 2 ? Real(0.25) : Real(2.0 / 3.0));
   const Real dt = Real(P->dt), cdt = cs * dt, dx_inv = Real(P->dx_inv), dz_inv = Real(P->dz_inv);
   const Real eps4 = Real(4.0 * P->weno_eps);
+  const int t = threadIdx.x, tx = t % kPlaneTileX, tz = t / kPlaneTileX;
   for (int v = blockIdx.x; v < nxt * nzt; v += gridDim.x) {
     int xt, zt;
     plane_tile(v, nxt, nzt, xt, zt);
-    const int x = xt * kPlaneTileX + int(threadIdx.x) % kPlaneTileX;
-    const int z = zt * kPlaneTileZ + int(threadIdx.x) / kPlaneTileX;
+    const int x0 = xt * kPlaneTileX, z0 = zt * kPlaneTileZ;
+    const int x = x0 + tx, z = z0 + tz;
     const bool valid = x < nx && z < nz;
-    const int xc = min(x, nx - 1), zc = min(z, nz - 1);
-    const int cell = zc * ldx + xc;
-    // the 7-point lines of this cell (outflow clamps), as plane offsets
-    int ox[7], oz[7];
+    const int cell = min(z, nz - 1) * ldx + min(x, nx - 1);
+    // this lane's share of the tile loads: plane offsets (clamped) and LDS slots
+    uint32_t loff[kTileLoads];
+    int lslot[kTileLoads];
 #pragma unroll
-    for (int d = 0; d < 7; ++d) {
-      ox[d] = zc * ldx + min(max(xc + d - 3, 0), nx - 1);
-      oz[d] = min(max(zc + d - 3, 0), nz - 1) * ldx + xc;
+    for (int q = 0; q < kTileLoads; ++q) {
+      const int e = t + 256 * q;
+      const int r = min(e, kTileElems - 1) / kTileCols, c = min(e, kTileElems - 1) % kTileCols;
+      const int gz = min(max(z0 - 3 + r, 0), nz - 1), gx = min(max(x0 - 3 + c, 0), nx - 1);
+      loff[q] = uint32_t(gz * ldx + gx);
+      lslot[q] = e < kTileElems ? r * kTileLd + c : -1;
     }
     // Landau frame of the stage input (FP64)
     double m[9];
@@ -173,6 +189,12 @@ __global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
                                      itab, as_const(a.aux), a.aux_pairs, D);
     const Real g0 = Real(M.gamma * P->tau_inv), gx = Real(M.ux * P->tau_inv), gz = Real(M.uz * P->tau_inv);
     double mom[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int Q = qp * qx * qh;
+    // first point's tile values
+    Real pre[kTileLoads];
+#pragma unroll
+    for (int q = 0; q < kTileLoads; ++q) pre[q] = a.fin[loff[q]];
+    int buf = 0;
 #pragma unroll 1
     for (int i = 0; i < qp; ++i) {
       Real Dc[NVT + 1];
@@ -187,38 +209,57 @@ __global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
       for (int j = 0; j < qx; ++j) {
         Real p6[6] = {Real(0), Real(0), Real(0), Real(0), Real(0), Real(0)};
         for (int k = 0; k < qh; ++k) {
-          const int64_t s = int64_t((i * qx + j) * qh + k);
+          const int s = (i * qx + j) * qh + k;
+          // 1. stage this point's tile, 2. prefetch the next point's values
+#pragma unroll
+          for (int q = 0; q < kTileLoads; ++q)
+            if (lslot[q] >= 0) (&tile[buf][0][0])[lslot[q]] = pre[q];
+          if (s + 1 < Q) {
+            const Real* nrow = a.fin + int64_t(s + 1) * plane;
+#pragma unroll
+            for (int q = 0; q < kTileLoads; ++q) pre[q] = nrow[loff[q]];
+          }
+          const Real fnv = HAS_FN ? a.fn[int64_t(s) * plane + cell] : Real(0);
+          __syncthreads();
+          // 3. this lane's left x face and lower z face (plus the tile's last
+          //    face of each row / column), upwinded by the point's velocity
           const cptr<Real> V = vtab + (j * qh + k) * kVStride;
           const Real vx = V[0], vz = V[1];
-          const Real* row = a.fin + s * plane;
-          Real fx[7], fz[7];
-#pragma unroll
-          for (int d = 0; d < 7; ++d) fx[d] = row[ox[d]];
-#pragma unroll
-          for (int d = 0; d < 7; ++d) fz[d] = d == 3 ? fx[3] : row[oz[d]];
-          Real hxl, hxr, hzl, hzr;
-          if (vx >= Real(0)) {
-            hxl = weno5(fx[0], fx[1], fx[2], fx[3], fx[4], eps4);
-            hxr = weno5(fx[1], fx[2], fx[3], fx[4], fx[5], eps4);
-          } else {
-            hxl = weno5(fx[5], fx[4], fx[3], fx[2], fx[1], eps4);
-            hxr = weno5(fx[6], fx[5], fx[4], fx[3], fx[2], eps4);
+          {
+            const Real* rw = &tile[buf][tz + 3][tx];  // columns tx .. tx+6 of this row
+            fxs[buf][tz][tx] = vx >= Real(0) ? weno5(rw[0], rw[1], rw[2], rw[3], rw[4], eps4)
+                                             : weno5(rw[5], rw[4], rw[3], rw[2], rw[1], eps4);
+            const Real* cl = &tile[buf][tz][tx + 3];  // rows tz .. tz+6 of this column
+            fzs[buf][tz][tx] = vz >= Real(0)
+                                   ? weno5(cl[0], cl[kTileLd], cl[2 * kTileLd], cl[3 * kTileLd], cl[4 * kTileLd], eps4)
+                                   : weno5(cl[5 * kTileLd], cl[4 * kTileLd], cl[3 * kTileLd], cl[2 * kTileLd],
+                                           cl[kTileLd], eps4);
+            if (tz == kPlaneTileZ - 1) {  // upper face of the last row
+              const Real* cu = cl + kTileLd;
+              fzs[buf][kPlaneTileZ][tx] =
+                  vz >= Real(0) ? weno5(cu[0], cu[kTileLd], cu[2 * kTileLd], cu[3 * kTileLd], cu[4 * kTileLd], eps4)
+                                : weno5(cu[5 * kTileLd], cu[4 * kTileLd], cu[3 * kTileLd], cu[2 * kTileLd],
+                                        cu[kTileLd], eps4);
+            }
+            if (t < kPlaneTileZ) {  // right face of the last column of row t
+              const Real* re = &tile[buf][t + 3][kPlaneTileX];
+              fxs[buf][t][kPlaneTileX] = vx >= Real(0) ? weno5(re[0], re[1], re[2], re[3], re[4], eps4)
+                                                       : weno5(re[5], re[4], re[3], re[2], re[1], eps4);
+            }
           }
-          if (vz >= Real(0)) {
-            hzl = weno5(fz[0], fz[1], fz[2], fz[3], fz[4], eps4);
-            hzr = weno5(fz[1], fz[2], fz[3], fz[4], fz[5], eps4);
-          } else {
-            hzl = weno5(fz[5], fz[4], fz[3], fz[2], fz[1], eps4);
-            hzr = weno5(fz[6], fz[5], fz[4], fz[3], fz[2], eps4);
-          }
+          __syncthreads();
+          // 4. update
+          const Real fr = tile[buf][tz + 3][tx + 3];
+          const Real hxl = fxs[buf][tz][tx], hxr = fxs[buf][tz][tx + 1];
+          const Real hzl = fzs[buf][tz][tx], hzr = fzs[buf][tz + 1][tx];
           const Real feq = legendre_series<Real, NVT>(Dc, vx * hx + vz * hz);
-          const Real fr = fx[3];
           const Real adv = (hxr - hxl) * (-vx * dx_inv) + (hzr - hzl) * (-vz * dz_inv);
           const Real rate = g0 - vx * gx - vz * gz;
           const Real L = adv - rate * (fr - feq);
-          const Real out = HAS_FN ? cdt * L + (cs * fr + cn * a.fn[s * plane + cell]) : fr + dt * L;
-          if (valid) a.fout[s * plane + cell] = out;
+          const Real out = HAS_FN ? cdt * L + (cs * fr + cn * fnv) : fr + dt * L;
+          if (valid) a.fout[int64_t(s) * plane + cell] = out;
           add_point(p6, V, out);
+          buf ^= 1;
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) acc.S[q].add(p6[q]);
@@ -232,6 +273,7 @@ __global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) a.rec_out[c * plane + cell] = mom[c];
     }
+    __syncthreads();  // the next tile reuses the LDS buffers
   }
 }
 

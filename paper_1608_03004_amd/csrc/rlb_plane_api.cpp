@@ -52,6 +52,15 @@ struct rlb_plane {
 
 namespace {
 
+// Device-to-device copy of a state: the library's 16-byte vector copy kernel
+// when both ends are 16-byte aligned, the runtime's copy otherwise (caller
+// buffers may be views at any element offset).
+hipError_t state_copy(void* dst, const void* src, size_t bytes, hipStream_t s) {
+  if (((reinterpret_cast<uintptr_t>(dst) | reinterpret_cast<uintptr_t>(src)) % 16) == 0)
+    return launch_copy(dst, src, bytes, s);
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+
 rlb_status pfail(rlb_plane* P, rlb_status st, const std::string& msg) {
   if (P) P->err = msg; else g_plane_create_error = msg;
   return st;
@@ -357,7 +366,7 @@ rlb_status rlb_plane_get_state(rlb_plane* P, void* dst) {
   rlb_status st = ready(P, true);
   if (st != RLB_OK) return st;
   if (!dst) return pfail(P, RLB_ERR_INVALID_ARG, "dst is NULL");
-  const hipError_t e = launch_copy(dst, P->ws + P->off_F[0], P->state_elems * P->rsize, P->stream);
+  const hipError_t e = state_copy(dst, P->ws + P->off_F[0], P->state_elems * P->rsize, P->stream);
   if (e != hipSuccess) return phip(P, e, "state copy");
   return RLB_OK;
 }
@@ -366,7 +375,7 @@ rlb_status rlb_plane_set_state(rlb_plane* P, const void* src) {
   rlb_status st = ready(P, false);
   if (st != RLB_OK) return st;
   if (!src) return pfail(P, RLB_ERR_INVALID_ARG, "src is NULL");
-  hipError_t e = launch_copy(P->ws + P->off_F[0], src, P->state_elems * P->rsize, P->stream);
+  hipError_t e = state_copy(P->ws + P->off_F[0], src, P->state_elems * P->rsize, P->stream);
   if (e == hipSuccess) e = P->prec == RLB_FP32 ? plane_records<float>(P) : plane_records<double>(P);
   if (e != hipSuccess) return phip(P, e, "state load");
   P->initialised = true;

@@ -436,3 +436,23 @@ def test_batched_seeded_tubes_against_oracle(torch_cuda):
         F, ref = _oracle_run(plist[k], w["left"][k], w["right"][k], 12)
         errs = field_errors(lat.moments(k), ref)
         assert max(e[0] for e in errs.values()) < 1e-5, (k, errs)
+
+
+def test_state_copies_into_unaligned_views(torch_cuda):
+    # caller buffers at any element offset: the copy falls back to the runtime's
+    torch = torch_cuda
+    for precision in ("fp64", "fp32"):
+        lat = _lattice([dict(nx=200, q_xi=8, q_p=3, tau=1e-2)], precision=precision)
+        lat.set_initial_state(SOD_L, SOD_R)
+        lat.step(3)
+        ref = lat.get_state().clone()
+        buf = torch.zeros(lat.state_elems + 1, dtype=lat.dtype, device=lat.device)
+        view = buf[1:]
+        lat.get_state(view)
+        lat.stream.synchronize()
+        assert torch.equal(view, ref)
+        lat.step(2)
+        after = lat.get_state().clone()
+        lat.set_state(view)
+        lat.step(2)
+        assert torch.equal(lat.get_state(), after)
