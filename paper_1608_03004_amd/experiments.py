@@ -25,7 +25,9 @@ DELTA_N = SOD_L[1] - SOD_R[1]
 
 
 def run_profile(nx, q_xi, tau, t_end, dt=None, precision="fp64", q_p=3):
-    """Fields [10, nx] at t_end (rounded to whole steps) and the exact end time."""
+    """Fields [10, nx] at t_end (rounded to whole steps) and the exact end time
+    (N_p = 2, N_v = 5 as in the paper; Q_xi >= 4 integrates T^{mu nu} of that
+    expansion exactly)."""
     kw = dict(nx=nx, q_xi=q_xi, q_p=q_p, n_v=5, n_p=2, tau=tau)
     if dt:
         kw["dt"] = dt
@@ -68,7 +70,7 @@ def error_measure(n, n_ref):
     return float(np.max(np.abs(n - n_ref)) / DELTA_N)
 
 
-def error_vs_order(nx=2000, t_end=0.25, taus=(1e-4, 1e-2, 1.0), orders=(2, 3, 4, 6, 8, 16, 32, 64), ref_order=200):
+def error_vs_order(nx=2000, t_end=0.25, taus=(1e-4, 1e-2, 1.0), orders=(4, 6, 8, 16, 32, 64), ref_order=200):
     out = {}
     for tau in taus:
         dt = min(0.5 / nx, 0.5 * tau)
