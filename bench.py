@@ -298,6 +298,21 @@ def plane_step_bytes(spec, rsize):
     return 8 * spec.nx * spec.nz * spec.Q * rsize + 3 * 144 * spec.nx * spec.nz
 
 
+# Vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one lane
+# operation per lane and cycle (FP32 without packed math, which the build
+# disables, and FP64 alike): 39.3 T operations/s, i.e. 78.6 TFLOP/s of FMAs.
+VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+
+
+def plane_point_ops(spec):
+    """Algorithmic vector operations per point and stage of the plane update:
+    two WENO5 faces of 37 operations each (difference form, one reciprocal),
+    the equilibrium polynomial in c = v . u_hat (2 + N_v), advection and
+    relaxation (8), the RK combination (3) and the six moment FMAs.  Per-cell
+    work (Landau frame, projection) and the tile's extra faces are excluded."""
+    return 2 * 37 + (2 + spec.n_v) + 8 + 3 + 6
+
+
 def leg_plane(precision, steps, warmup=2):
     """The multi-dimensional model: a 1024 x 1024 plane, Q = 3 x 8 x 5 evolved
     points (Q_phi = 8), a 2D Riemann problem."""
@@ -323,6 +338,7 @@ def leg_plane(precision, steps, warmup=2):
     launch_s = ev / (3 * steps)
     bytes_launch = plane_step_bytes(spec, rsize) / 3
     pts = spec.nx * spec.nz * spec.Q
+    ops_launch = plane_point_ops(spec) * pts
     res = dict(value=pts * steps / wall, unit="cell*quad-point updates/s", ms_per_step=1e3 * wall / steps,
                steps=steps,
                roofline=dict(bound="hbm", achieved=round(bytes_launch / launch_s / 1e9, 1), peak=HBM_PEAK_GBS,
@@ -330,6 +346,9 @@ def leg_plane(precision, steps, warmup=2):
                              traffic=measured_traffic(precision, "plane_stage_kernel"), kernel="plane_stage_kernel",
                              bytes_per_launch=int(bytes_launch),
                              launch_us=round(launch_s * 1e6, 2)),
+               roofline_alu=dict(bound="alu", achieved=round(ops_launch / launch_s / 1e9, 1), peak=VALU_PEAK_GOPS,
+                                 unit="Gop/s", frac=round(ops_launch / launch_s / 1e9 / VALU_PEAK_GOPS, 4),
+                                 kernel="plane_stage_kernel", ops_per_point=plane_point_ops(spec)),
                workload=f"plane_quadrants: 1024 x 1024 cells, Q = 3 x 8 x (8/2+1) = 120, N_v = 5, tau = 1e-2, "
                         f"2D Riemann problem, {precision.upper()}")
     del gp

@@ -249,7 +249,9 @@ const char* rlb_last_error(const rlb_lattice* lat);
  * Cells are cell-centred on [x_min, x_max] x [z_min, z_max]; every edge is an
  * outflow (zero-gradient) boundary.
  *
- *   nx, nz     -- cells, 8 <= each, nx * nz <= 2^26;
+ *   nx, nz     -- cells, 8 <= each, nx * nz <= 2^26 and, with rows padded
+ *                 to 64 cells, ceil(nx/64)*64 * nz <= 2^27 (one point's plane
+ *                 is addressed with 32-bit byte offsets);
  *   q_xi, q_phi, q_p, n_v, n_p -- as for a tube (n_v <= 7), plus
  *                 n_v + 3 <= q_phi <= 64 (the azimuthal rule integrates the
  *                 moments of the equilibrium exactly);

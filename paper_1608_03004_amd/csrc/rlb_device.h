@@ -34,6 +34,43 @@ __device__ inline double fast_div(double n, double d) {
   return fma(r, fma(-d, q, n), q);
 }
 
+// Raw buffer resources: a scalar base and size, accessed with a 32-bit
+// per-lane byte offset and a scalar byte offset, so that loads and stores carry
+// no per-lane 64-bit address arithmetic.  AUX is the cache policy
+// (0: default, 2: non-temporal).
+using Rsrc = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;  // word 3 of a raw 32-bit-format resource (gfx950)
+
+__device__ inline Rsrc make_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), kRsrcWord3);
+}
+
+template <typename Real>
+struct BufIO;
+template <>
+struct BufIO<float> {
+  template <int AUX>
+  static __device__ inline float load(Rsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), AUX));
+  }
+  template <int AUX>
+  static __device__ inline void store(float v, Rsrc r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(voff), int(soff), AUX);
+  }
+};
+template <>
+struct BufIO<double> {
+  using V2 = uint32_t __attribute__((ext_vector_type(2)));
+  template <int AUX>
+  static __device__ inline double load(Rsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), AUX));
+  }
+  template <int AUX>
+  static __device__ inline void store(double v, Rsrc r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, int(voff), int(soff), AUX);
+  }
+};
+
 // ---------------------------------------------------------------------------
 // Small arithmetic helpers
 // ---------------------------------------------------------------------------

@@ -116,46 +116,14 @@ __device__ inline void load_record(const double* rec, int64_t ldx, int x, double
 // ---------------------------------------------------------------------------
 // Stage kernel
 // ---------------------------------------------------------------------------
-// Raw buffer resources.  In the chunk loop every access is a scalar base
-// (per chunk), a scalar row offset and a 32-bit per-lane byte offset, so the
-// loads and stores carry no per-lane 64-bit address arithmetic; the resource's
-// size bounds every access to the chunk's rows.
-using Rsrc = __amdgpu_buffer_rsrc_t;
-constexpr int kRsrcWord3 = 0x00020000;  // word 3 of a raw 32-bit-format resource (gfx950)
-
-__device__ inline Rsrc make_rsrc(const void* base, uint32_t bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, int(bytes), kRsrcWord3);
-}
-
 // Cache policies of the buffer accesses (0: default, 2: non-temporal).  f^n
 // and the stage output are touched once per stage and stream past the caches;
 // the stage input keeps the default policy because neighbouring tiles re-read
-// its halo lines from L2 (non-temporal there measured 6 % slower).
+// its halo lines from L2 (non-temporal there measured 6 % slower).  In the
+// chunk loop every access is a scalar base (per chunk), a scalar row offset and
+// a 32-bit per-lane byte offset; the resource's size bounds every access to the
+// chunk's rows.
 constexpr int kLoadAux = 0, kFnAux = 2, kStoreAux = 2;
-
-template <typename Real>
-struct BufIO;
-template <>
-struct BufIO<float> {
-  template <int AUX = kLoadAux>
-  static __device__ inline float load(Rsrc r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, int(voff), int(soff), AUX));
-  }
-  static __device__ inline void store(float v, Rsrc r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, int(voff), int(soff), kStoreAux);
-  }
-};
-template <>
-struct BufIO<double> {
-  using V2 = uint32_t __attribute__((ext_vector_type(2)));
-  template <int AUX = kLoadAux>
-  static __device__ inline double load(Rsrc r, uint32_t voff, uint32_t soff) {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(voff), int(soff), AUX));
-  }
-  static __device__ inline void store(double v, Rsrc r, uint32_t voff, uint32_t soff) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), r, int(voff), int(soff), kStoreAux);
-  }
-};
 
 // The CH rows of chunk (i, j0) of one tube's distribution: rows i*qx + j0 + c,
 // with rows past the last point repeating the last row (so every lane always
@@ -184,12 +152,12 @@ __device__ inline void issue_chunk(const Real* tube_f, int64_t ldx, uint32_t row
                                    uint32_t vx, int t, int x0, int nx, ChunkLoads<Real, CH>& L) {
   const ChunkRows<Real, CH> rows(tube_f, ldx, row_bytes, qx, i, j0);
 #pragma unroll
-  for (int c = 0; c < CH; ++c) L.f[c] = BufIO<Real>::load(rows.r, vx, rows.soff(c, row_bytes));
+  for (int c = 0; c < CH; ++c) L.f[c] = BufIO<Real>::template load<kLoadAux>(rows.r, vx, rows.soff(c, row_bytes));
   if (t < 64) {  // wave 0: lane h + 6c loads halo cell h of chunk point c
     const int c = min(t / 6, CH - 1), h = t % 6;
     const int hx = h < 3 ? max(x0 - 3 + h, 0) : min(x0 + TILE + (h - 3), nx - 1);
     const uint32_t off = uint32_t(min(c, rows.last)) * row_bytes + uint32_t(hx) * uint32_t(sizeof(Real));
-    L.halo = BufIO<Real>::load(rows.r, off, 0);
+    L.halo = BufIO<Real>::template load<kLoadAux>(rows.r, off, 0);
   }
 }
 
@@ -398,7 +366,7 @@ void stage_kernel(StageArgs<Real> a) {
               // the RK combination of the stage input and f^n is formed first,
               // so that a state with L = 0 is reproduced exactly
               const Real out = HAS_FN ? cdt * L + (cs * fr + cn * nr[c]) : fr + dt * L;
-              if (valid) BufIO<Real>::store(out, orow.r, vx, uint32_t(c) * row_bytes);
+              if (valid) BufIO<Real>::template store<kStoreAux>(out, orow.r, vx, uint32_t(c) * row_bytes);
               p0 += J[1] * out;
               p1 += J[2] * out;
               p2 += J[3] * out;

@@ -14,20 +14,27 @@
 // -> the truncated equilibrium, which depends on the direction only through
 // c = v . u_hat: the coefficients of the 1D projection at the speed |u|
 // (eq. feqtrunc; the projection onto polynomials of degree <= N_v on the
-// sphere of a function of v . u_hat is its Legendre series in c) evaluated by
-// the Legendre recurrence at each point -> WENO5 faces in x and z, relaxation,
-// RK combination, store, and the nine moments of the output.
+// sphere of a function of v . u_hat is its Legendre series in c), turned into
+// a polynomial in c once per cell and radial node and evaluated by Horner's
+// rule at each point -> WENO5 faces in x and z, relaxation, RK combination,
+// store, and the nine moments of the output.
 //
 // Work decomposition: one lane per cell, workgroups of 64 x 4 cells (x
 // contiguous in memory).  For every point the workgroup stages the cells of
 // its tile and a 3-cell halo on each side (outflow clamps applied at load
 // time) in LDS, the next point's values already in flight in registers; each
 // lane computes the WENO value of its own left x face and lower z face (the
-// tile's last faces by a few extra lanes), shares them through LDS and forms
-// the update from its two x and two z faces.  Two barriers per point, double
-// buffered.  Tiles are ordered z-fastest within an x column and handed to the
-// XCDs in runs, so the z halos of a tile come from the same L2.
+// tile's last row and column of faces by a wave that rotates with the
+// workgroup and the point), shares them through LDS and forms the update from
+// its two x and two z faces.  Two barriers per point, double buffered, with
+// the point loop unrolled by two so that every LDS access of the common path
+// is one per-lane offset plus an immediate; global accesses are buffer
+// accesses with a scalar base per point and 32-bit per-lane offsets.  Tiles
+// are ordered z-fastest within an x column and handed to the XCDs in runs, so
+// the z halos of a tile come from the same L2.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "rlb_device.h"
 #include "rlb_internal.h"
@@ -89,19 +96,42 @@ __device__ inline Macro2 landau2(const double m[9]) {
   return M;
 }
 
-// Sum of the truncated series sum_k D[k] P_k(c), Legendre recurrence.
+// Monomial coefficients of the Legendre polynomials, P_k(c) = sum_m L[k][m] c^m,
+// from the three-term recurrence (k+1) P_{k+1} = (2k+1) c P_k - k P_{k-1}.
+struct LegendreMonomials {
+  double c[kMaxNv + 1][kMaxNv + 1];
+};
+constexpr LegendreMonomials legendre_monomials() {
+  LegendreMonomials L{};
+  L.c[0][0] = 1.0;
+  L.c[1][1] = 1.0;
+  for (int k = 1; k < kMaxNv; ++k)
+    for (int m = 0; m <= k + 1; ++m)
+      L.c[k + 1][m] = ((2.0 * k + 1.0) * (m > 0 ? L.c[k][m - 1] : 0.0) - k * L.c[k - 1][m]) / (k + 1.0);
+  return L;
+}
+constexpr LegendreMonomials kLegendre = legendre_monomials();
+
+// The truncated series sum_k D[k] P_k(c) as a polynomial in c: coefficients
+// a[m] = sum_k D[k] L[k][m] (once per cell and radial node), then Horner's
+// rule per point.
 template <typename Real, int NVT>
-__device__ inline Real legendre_series(const Real D[NVT + 1], Real c) {
-  Real p0 = Real(1), p1 = c;
-  Real acc = D[0] + D[1] * c;
+__device__ inline void series_monomials(const Real D[NVT + 1], Real a[NVT + 1]) {
 #pragma unroll
-  for (int k = 1; k < NVT; ++k) {
-    const Real p2 = Real((2.0 * k + 1.0) / (k + 1.0)) * c * p1 - Real(double(k) / (k + 1.0)) * p0;
-    acc += D[k + 1] * p2;
-    p0 = p1;
-    p1 = p2;
+  for (int m = 0; m <= NVT; ++m) {
+    Real acc = Real(0);
+#pragma unroll
+    for (int k = m; k <= NVT; ++k)
+      if (kLegendre.c[k][m] != 0.0) acc += D[k] * Real(kLegendre.c[k][m]);
+    a[m] = acc;
   }
-  return acc;
+}
+template <typename Real, int NVT>
+__device__ inline Real horner(const Real a[NVT + 1], Real c) {
+  Real f = a[NVT];
+#pragma unroll
+  for (int m = NVT - 1; m >= 0; --m) f = f * c + a[m];
+  return f;
 }
 
 // Moment sums of one radial node, in the order every kernel uses: plain
@@ -134,20 +164,54 @@ __device__ inline void plane_tile(int v, int nxt, int nzt, int& xt, int& zt) {
   zt = item % nzt;
 }
 
-// LDS tile of one point: rows z0-3 .. z0+6, columns x0-3 .. x0+66 (outflow
-// clamps applied at load time), padded to kTileLd columns.
-constexpr int kTileRows = kPlaneTileZ + 6, kTileCols = kPlaneTileX + 6, kTileLd = kTileCols + 2;
+// LDS of one point (two buffers, alternating between points): the tile with a
+// 3-cell halo (rows z0-3 .. z0+6, columns x0-3 .. x0+66, outflow clamps
+// applied at load time), then the x faces (left face of columns 0 .. 64 of
+// each row) and the z faces (lower face of rows 0 .. 4 of each column).  All
+// three share the row stride kLd, so that every access of the common path is
+// one per-lane offset plus an immediate.
+constexpr int kLd = kPlaneTileX + 8;
+constexpr int kTileRows = kPlaneTileZ + 6, kTileCols = kPlaneTileX + 6;
 constexpr int kTileElems = kTileRows * kTileCols;
 constexpr int kTileLoads = (kTileElems + 255) / 256;  // per lane
+constexpr int kFxOff = kTileRows * kLd, kFzOff = kFxOff + kPlaneTileZ * kLd;
+constexpr int kBufElems = kFzOff + (kPlaneTileZ + 1) * kLd;
+static_assert(kLd >= kTileCols && kLd >= kPlaneTileX + 1, "row stride");
+static_assert(kPlaneTileX == 64 && kPlaneTileZ == 4, "one wave per tile row");
+
+template <int B>
+using BufTag = std::integral_constant<int, B>;
+
+// WENO5 value at a face from the six cells p[0], p[ST], .. p[5 ST] around it,
+// upwinded by the sign of the velocity component (cells 0 .. 4 for up,
+// 5 .. 1 otherwise).  `up` is wave-uniform; the empty asm statement keeps the
+// two orientations as separate branches, each reading LDS at immediate
+// offsets, instead of one merged body that computes its LDS addresses.
+template <typename Real, int ST>
+__device__ inline Real face(const Real* p, bool up, Real eps4) {
+  if (up) return weno5(p[0], p[ST], p[2 * ST], p[3 * ST], p[4 * ST], eps4);
+  Real h = weno5(p[5 * ST], p[4 * ST], p[3 * ST], p[2 * ST], p[ST], eps4);
+  asm volatile("" : "+v"(h));
+  return h;
+}
+
+// Occupancy: 5 waves per SIMD for FP32 and 4 for FP64 with Q_p <= 4 (the
+// per-cell coefficients of the other radial nodes and a few tile constants
+// spill, outside the point loop); the generic Q_p <= 8 group is left to the
+// compiler.
+template <typename Real, int QPT>
+constexpr int plane_waves_per_eu() {
+  return QPT > 4 ? 1 : (sizeof(Real) == 4 ? 5 : 4);
+}
 
 template <typename Real, int QPT, int NVT, bool HAS_FN>
-__global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
-  __shared__ Real tile[2][kTileRows][kTileLd];
-  __shared__ Real fxs[2][kPlaneTileZ][kPlaneTileX + 1];  // x faces: left face of column q
-  __shared__ Real fzs[2][kPlaneTileZ + 1][kPlaneTileX];  // z faces: lower face of row r
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<Real, QPT>())))
+void plane_stage_kernel(PlaneArgs<Real> a) {
+  __shared__ Real lds[2 * kBufElems];
   const cptr<PlaneDev> P = as_const(a.pl);
   const int nx = P->nx, nz = P->nz, ldx = P->ldx, qx = P->qx, qh = P->qh, qp = P->qp;
   const int64_t plane = P->plane;
+  const uint32_t plane_bytes = uint32_t(plane * int64_t(sizeof(Real)));
   const int nxt = (nx + kPlaneTileX - 1) / kPlaneTileX, nzt = (nz + kPlaneTileZ - 1) / kPlaneTileZ;
   const cptr<Real> vtab = as_const(a.vtab);
   const cptr<double> itab = as_const(a.itab);
@@ -157,6 +221,8 @@ __global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
   const Real dt = Real(P->dt), cdt = cs * dt, dx_inv = Real(P->dx_inv), dz_inv = Real(P->dz_inv);
   const Real eps4 = Real(4.0 * P->weno_eps);
   const int t = threadIdx.x, tx = t % kPlaneTileX, tz = t / kPlaneTileX;
+  const int lane_off = tz * kLd + tx;
+  const int wave = __builtin_amdgcn_readfirstlane(tz);
   for (int v = blockIdx.x; v < nxt * nzt; v += gridDim.x) {
     int xt, zt;
     plane_tile(v, nxt, nzt, xt, zt);
@@ -164,7 +230,9 @@ __global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
     const int x = x0 + tx, z = z0 + tz;
     const bool valid = x < nx && z < nz;
     const int cell = min(z, nz - 1) * ldx + min(x, nx - 1);
-    // this lane's share of the tile loads: plane offsets (clamped) and LDS slots
+    const uint32_t cell_b = uint32_t(cell) * uint32_t(sizeof(Real));
+    // this lane's share of the tile loads: byte offsets in a point's plane
+    // (clamped) and LDS slots
     uint32_t loff[kTileLoads];
     int lslot[kTileLoads];
 #pragma unroll
@@ -172,8 +240,8 @@ __global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
       const int e = t + 256 * q;
       const int r = min(e, kTileElems - 1) / kTileCols, c = min(e, kTileElems - 1) % kTileCols;
       const int gz = min(max(z0 - 3 + r, 0), nz - 1), gx = min(max(x0 - 3 + c, 0), nx - 1);
-      loff[q] = uint32_t(gz * ldx + gx);
-      lslot[q] = e < kTileElems ? r * kTileLd + c : -1;
+      loff[q] = uint32_t(gz * ldx + gx) * uint32_t(sizeof(Real));
+      lslot[q] = e < kTileElems ? r * kLd + c : -1;
     }
     // Landau frame of the stage input (FP64)
     double m[9];
@@ -192,9 +260,12 @@ __global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
     const int Q = qp * qx * qh;
     // first point's tile values
     Real pre[kTileLoads];
+    {
+      const Rsrc r0 = make_rsrc(a.fin, plane_bytes);
 #pragma unroll
-    for (int q = 0; q < kTileLoads; ++q) pre[q] = a.fin[loff[q]];
-    int buf = 0;
+      for (int q = 0; q < kTileLoads; ++q) pre[q] = BufIO<Real>::template load<0>(r0, loff[q], 0);
+    }
+    int s = 0;
 #pragma unroll 1
     for (int i = 0; i < qp; ++i) {
       Real Dc[NVT + 1];
@@ -205,61 +276,67 @@ __global__ __launch_bounds__(256) void plane_stage_kernel(PlaneArgs<Real> a) {
         for (int ii = 1; ii < QPT; ++ii) d = i == ii ? D[ii][k] : d;
         Dc[k] = d;
       }
+      Real Am[NVT + 1];
+      series_monomials<Real, NVT>(Dc, Am);
       PlaneSums<Real> acc;
+#pragma unroll 1
       for (int j = 0; j < qx; ++j) {
         Real p6[6] = {Real(0), Real(0), Real(0), Real(0), Real(0), Real(0)};
-        for (int k = 0; k < qh; ++k) {
-          const int s = (i * qx + j) * qh + k;
+        // One point s = (i qx + j) qh + k with its values staged in buffer B.
+        auto point = [&](auto tag, int k) {
+          constexpr int B = decltype(tag)::value * kBufElems;
+          Real* const L = lds + B;
           // 1. stage this point's tile, 2. prefetch the next point's values
 #pragma unroll
           for (int q = 0; q < kTileLoads; ++q)
-            if (lslot[q] >= 0) (&tile[buf][0][0])[lslot[q]] = pre[q];
+            if (lslot[q] >= 0) L[lslot[q]] = pre[q];
           if (s + 1 < Q) {
-            const Real* nrow = a.fin + int64_t(s + 1) * plane;
+            const Rsrc rn = make_rsrc(a.fin + int64_t(s + 1) * plane, plane_bytes);
 #pragma unroll
-            for (int q = 0; q < kTileLoads; ++q) pre[q] = nrow[loff[q]];
+            for (int q = 0; q < kTileLoads; ++q) pre[q] = BufIO<Real>::template load<0>(rn, loff[q], 0);
           }
-          const Real fnv = HAS_FN ? a.fn[int64_t(s) * plane + cell] : Real(0);
+          const Real fnv =
+              HAS_FN ? BufIO<Real>::template load<2>(make_rsrc(a.fn + int64_t(s) * plane, plane_bytes), cell_b, 0)
+                     : Real(0);
           __syncthreads();
-          // 3. this lane's left x face and lower z face (plus the tile's last
-          //    face of each row / column), upwinded by the point's velocity
+          // 3. this lane's left x face and lower z face, upwinded by the
+          //    point's velocity; the tile's upper z faces and right x faces go
+          //    to a wave that rotates with the workgroup and the point, so
+          //    that every SIMD carries the same share of them
           const cptr<Real> V = vtab + (j * qh + k) * kVStride;
           const Real vx = V[0], vz = V[1];
-          {
-            const Real* rw = &tile[buf][tz + 3][tx];  // columns tx .. tx+6 of this row
-            fxs[buf][tz][tx] = vx >= Real(0) ? weno5(rw[0], rw[1], rw[2], rw[3], rw[4], eps4)
-                                             : weno5(rw[5], rw[4], rw[3], rw[2], rw[1], eps4);
-            const Real* cl = &tile[buf][tz][tx + 3];  // rows tz .. tz+6 of this column
-            fzs[buf][tz][tx] = vz >= Real(0)
-                                   ? weno5(cl[0], cl[kTileLd], cl[2 * kTileLd], cl[3 * kTileLd], cl[4 * kTileLd], eps4)
-                                   : weno5(cl[5 * kTileLd], cl[4 * kTileLd], cl[3 * kTileLd], cl[2 * kTileLd],
-                                           cl[kTileLd], eps4);
-            if (tz == kPlaneTileZ - 1) {  // upper face of the last row
-              const Real* cu = cl + kTileLd;
-              fzs[buf][kPlaneTileZ][tx] =
-                  vz >= Real(0) ? weno5(cu[0], cu[kTileLd], cu[2 * kTileLd], cu[3 * kTileLd], cu[4 * kTileLd], eps4)
-                                : weno5(cu[5 * kTileLd], cu[4 * kTileLd], cu[3 * kTileLd], cu[2 * kTileLd],
-                                        cu[kTileLd], eps4);
-            }
-            if (t < kPlaneTileZ) {  // right face of the last column of row t
-              const Real* re = &tile[buf][t + 3][kPlaneTileX];
-              fxs[buf][t][kPlaneTileX] = vx >= Real(0) ? weno5(re[0], re[1], re[2], re[3], re[4], eps4)
-                                                       : weno5(re[5], re[4], re[3], re[2], re[1], eps4);
-            }
-          }
+          const bool ux = vx >= Real(0), uz = vz >= Real(0);
+          const Real* T = L + lane_off;
+          L[kFxOff + lane_off] = face<Real, 1>(T + 3 * kLd, ux, eps4);
+          L[kFzOff + lane_off] = face<Real, kLd>(T + 3, uz, eps4);
+          const int wz = (int(blockIdx.x) + s) & 3;
+          if (wave == wz)
+            L[kFzOff + kPlaneTileZ * kLd + tx] = face<Real, kLd>(L + kPlaneTileZ * kLd + 3 + tx, uz, eps4);
+          if (wave == (wz ^ 2) && tx < kPlaneTileZ)
+            L[kFxOff + tx * kLd + kPlaneTileX] = face<Real, 1>(L + (tx + 3) * kLd + kPlaneTileX, ux, eps4);
           __syncthreads();
           // 4. update
-          const Real fr = tile[buf][tz + 3][tx + 3];
-          const Real hxl = fxs[buf][tz][tx], hxr = fxs[buf][tz][tx + 1];
-          const Real hzl = fzs[buf][tz][tx], hzr = fzs[buf][tz + 1][tx];
-          const Real feq = legendre_series<Real, NVT>(Dc, vx * hx + vz * hz);
+          const Real fr = T[3 * kLd + 3];
+          const Real hxl = L[kFxOff + lane_off], hxr = L[kFxOff + lane_off + 1];
+          const Real hzl = L[kFzOff + lane_off], hzr = L[kFzOff + lane_off + kLd];
+          const Real feq = horner<Real, NVT>(Am, vx * hx + vz * hz);
           const Real adv = (hxr - hxl) * (-vx * dx_inv) + (hzr - hzl) * (-vz * dz_inv);
           const Real rate = g0 - vx * gx - vz * gz;
-          const Real L = adv - rate * (fr - feq);
-          const Real out = HAS_FN ? cdt * L + (cs * fr + cn * fnv) : fr + dt * L;
-          if (valid) a.fout[int64_t(s) * plane + cell] = out;
+          const Real Lr = adv - rate * (fr - feq);
+          const Real out = HAS_FN ? cdt * Lr + (cs * fr + cn * fnv) : fr + dt * Lr;
+          if (valid)
+            BufIO<Real>::template store<2>(out, make_rsrc(a.fout + int64_t(s) * plane, plane_bytes), cell_b, 0);
           add_point(p6, V, out);
-          buf ^= 1;
+          ++s;
+        };
+        int k = 0;
+        for (; k + 1 < qh; k += 2) {
+          point(BufTag<0>{}, k);
+          point(BufTag<1>{}, k + 1);
+        }
+        if (k < qh) {
+          point(BufTag<0>{}, k);
+          __syncthreads();  // the next point reuses buffer 0
         }
 #pragma unroll
         for (int q = 0; q < 6; ++q) acc.S[q].add(p6[q]);
@@ -306,13 +383,15 @@ __global__ __launch_bounds__(256) void plane_init_kernel(PlaneArgs<Real> a) {
 #pragma unroll
     for (int i = 0; i < QPT; ++i) {
       if (i < qp) {
+        Real Am[NVT + 1];
+        series_monomials<Real, NVT>(D[i], Am);
         PlaneSums<Real> acc;
         for (int j = 0; j < qx; ++j) {
           Real p6[6] = {Real(0), Real(0), Real(0), Real(0), Real(0), Real(0)};
           for (int k = 0; k < qh; ++k) {
             const int64_t s = int64_t((i * qx + j) * qh + k);
             const cptr<Real> V = vtab + (j * qh + k) * kVStride;
-            const Real f = legendre_series<Real, NVT>(D[i], V[0] * hx + V[1] * hz);
+            const Real f = horner<Real, NVT>(Am, V[0] * hx + V[1] * hz);
             a.fout[s * plane + cell] = f;
             add_point(p6, V, f);
           }

@@ -83,6 +83,8 @@ rlb_status validate_plane(const rlb_plane_desc& d, std::string& msg) {
   };
   if (d.nx < 8 || d.nz < 8) return bad("nx and nz must be >= 8");
   if (int64_t(d.nx) * d.nz > (int64_t(1) << 26)) return bad("nx * nz must be <= 2^26");
+  if (int64_t((d.nx + 63) / 64 * 64) * d.nz > (int64_t(1) << 27))
+    return bad("the padded plane (nx rounded up to 64) * nz must be <= 2^27 cells");
   if (d.q_xi < 1 || d.q_xi > 4096) return bad("q_xi must be in [1, 4096]");
   if (d.q_p < 1 || d.q_p > kMaxQp) return bad("q_p must be in [1, 8]");
   if (d.n_v < 0 || d.n_v > kMaxNv) return bad("n_v must be in [0, 7]");

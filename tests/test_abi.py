@@ -158,6 +158,7 @@ def _plane_create(lib, spec, prec=rlb.RLB_FP64):
     (dict(nx=4), rlb.RLB_ERR_INVALID_ARG),
     (dict(nz=7), rlb.RLB_ERR_INVALID_ARG),
     (dict(nx=1 << 14, nz=1 << 13), rlb.RLB_ERR_INVALID_ARG),        # more than 2^26 cells
+    (dict(nx=8, nz=1 << 22), rlb.RLB_ERR_INVALID_ARG),              # 2^25 cells, 2^28 padded
     (dict(q_phi=7), rlb.RLB_ERR_INVALID_ARG),                       # q_phi < n_v + 3
     (dict(q_phi=65), rlb.RLB_ERR_INVALID_ARG),
     (dict(n_v=8), rlb.RLB_ERR_INVALID_ARG),
