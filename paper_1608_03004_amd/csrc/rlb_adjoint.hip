@@ -28,12 +28,14 @@ namespace {
 
 using namespace dev;
 
-// adj_reduce: a block holds kRedCells cells (one per lane) and kRedGroups
-// groups of lanes (one wave each).  The groups split the quadrature points of
-// the reduction and the auxiliary node pairs of the projection's adjoint;
-// partial sums are combined through LDS in a fixed group order, so the result
-// is deterministic.
-constexpr int kRedCells = 64, kRedGroups = 4;
+// adj_reduce: a block holds kRedCells cells and kRedGroups groups of
+// kRedCells lanes (two groups per wave), one lane per cell in each group.  The
+// groups split the quadrature points of the reduction and the auxiliary node
+// pairs of the projection's adjoint; partial sums are combined through LDS in
+// a fixed group order, so the result is deterministic.  32 cells per block
+// doubles the blocks of a small tube over 64 (the adjoint is latency-bound at
+// its sizes: +9 % adjoint steps/s on 4096 cells x 96 points).
+constexpr int kRedCells = 32, kRedGroups = 8;
 
 // acc[d][lane] = sum over groups (in group order) of part[d]; every group
 // reads the same combined values afterwards.  Ends with a barrier.
