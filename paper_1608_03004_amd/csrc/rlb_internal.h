@@ -188,7 +188,7 @@ hipError_t launch_combine(const TubeDev* tubes, const WorkItem* items, int nitem
 // Velocity table row per (j, k): v_x, v_z, then the weighted moment factors
 // w, w v_x, w v_z, w v_x^2, w v_x v_z, w v_z^2 with w = w_xi[j] omega[k].
 constexpr int kVStride = 8;
-constexpr int kPlaneTileX = 64, kPlaneTileZ = 4;  // cells per workgroup
+constexpr int kPlaneTileX = 64, kPlaneTileZ = 4;  // cells per workgroup (init, moments)
 
 struct PlaneDev {
   int32_t nx, nz, ldx;
@@ -214,6 +214,8 @@ struct PlaneArgs {
   const double* init;  // init kernel: per-cell P, n, u^x, u^z [4][nz][nx]
 };
 
+// Workgroups of the stage kernel's grid (its tiles are taller than kPlaneTileZ).
+int plane_stage_grid(int nx, int nz);
 hipError_t launch_plane_stage(int prec_fp32, int qpt, int nvt, const void* args, int grid, hipStream_t stream);
 hipError_t launch_plane_init(int prec_fp32, int qpt, int nvt, const void* args, int grid, hipStream_t stream);
 hipError_t launch_plane_moments(int prec_fp32, const void* args, int grid, hipStream_t stream);

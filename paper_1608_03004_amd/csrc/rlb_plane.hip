@@ -19,10 +19,11 @@
 // rule at each point -> WENO5 faces in x and z, relaxation, RK combination,
 // store, and the nine moments of the output.
 //
-// Work decomposition: one lane per cell, workgroups of 64 x 4 cells (x
-// contiguous in memory).  For every point the workgroup stages the cells of
-// its tile and a 3-cell halo on each side (outflow clamps applied at load
-// time) in LDS, the next point's values already in flight in registers; each
+// Work decomposition: one lane per cell, stage workgroups of 64 x 8 cells
+// (x contiguous in memory, one wave per row).  For every point the workgroup
+// stages the cells of its tile and a 3-cell halo on each side (outflow clamps
+// applied at load time) in LDS, the next point's values already in flight in
+// registers; each
 // lane computes the WENO value of its own left x face and lower z face (the
 // tile's last row and column of faces by a wave that rotates with the
 // workgroup and the point), shares them through LDS and forms the update from
@@ -165,19 +166,20 @@ __device__ inline void plane_tile(int v, int nxt, int nzt, int& xt, int& zt) {
 }
 
 // LDS of one point (two buffers, alternating between points): the tile with a
-// 3-cell halo (rows z0-3 .. z0+6, columns x0-3 .. x0+66, outflow clamps
+// 3-cell halo (rows z0-3 .. z0+kTZ+2, columns x0-3 .. x0+66, outflow clamps
 // applied at load time), then the x faces (left face of columns 0 .. 64 of
-// each row) and the z faces (lower face of rows 0 .. 4 of each column).  All
-// three share the row stride kLd, so that every access of the common path is
-// one per-lane offset plus an immediate.
+// each row) and the z faces (lower face of rows 0 .. kTZ of each column).
+// All three share the row stride kLd, so that every access of the common path
+// is one per-lane offset plus an immediate.
+constexpr int kTZ = 8, kThreads = kPlaneTileX * kTZ;  // stage tile rows, threads
 constexpr int kLd = kPlaneTileX + 8;
-constexpr int kTileRows = kPlaneTileZ + 6, kTileCols = kPlaneTileX + 6;
+constexpr int kTileRows = kTZ + 6, kTileCols = kPlaneTileX + 6;
 constexpr int kTileElems = kTileRows * kTileCols;
-constexpr int kTileLoads = (kTileElems + 255) / 256;  // per lane
-constexpr int kFxOff = kTileRows * kLd, kFzOff = kFxOff + kPlaneTileZ * kLd;
-constexpr int kBufElems = kFzOff + (kPlaneTileZ + 1) * kLd;
+constexpr int kTileLoads = (kTileElems + kThreads - 1) / kThreads;  // per lane
+constexpr int kFxOff = kTileRows * kLd, kFzOff = kFxOff + kTZ * kLd;
+constexpr int kBufElems = kFzOff + (kTZ + 1) * kLd;
 static_assert(kLd >= kTileCols && kLd >= kPlaneTileX + 1, "row stride");
-static_assert(kPlaneTileX == 64 && kPlaneTileZ == 4, "one wave per tile row");
+static_assert(kPlaneTileX == 64, "one wave per tile row");
 
 template <int B>
 using BufTag = std::integral_constant<int, B>;
@@ -195,24 +197,24 @@ __device__ inline Real face(const Real* p, bool up, Real eps4) {
   return h;
 }
 
-// Occupancy: 5 waves per SIMD for FP32 and 4 for FP64 with Q_p <= 4 (the
-// per-cell coefficients of the other radial nodes and a few tile constants
-// spill, outside the point loop); the generic Q_p <= 8 group is left to the
-// compiler.
+// Occupancy: 6 waves per SIMD (three workgroups) for FP32 and 4 for FP64
+// with Q_p <= 4 (the per-cell coefficients of the other radial nodes and a few
+// tile constants spill, outside the point loop); the generic Q_p <= 8 group is
+// left to the compiler.
 template <typename Real, int QPT>
 constexpr int plane_waves_per_eu() {
-  return QPT > 4 ? 1 : (sizeof(Real) == 4 ? 5 : 4);
+  return QPT > 4 ? 1 : (sizeof(Real) == 4 ? 6 : 4);
 }
 
 template <typename Real, int QPT, int NVT, bool HAS_FN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<Real, QPT>())))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<Real, QPT>())))
 void plane_stage_kernel(PlaneArgs<Real> a) {
   __shared__ Real lds[2 * kBufElems];
   const cptr<PlaneDev> P = as_const(a.pl);
   const int nx = P->nx, nz = P->nz, ldx = P->ldx, qx = P->qx, qh = P->qh, qp = P->qp;
   const int64_t plane = P->plane;
   const uint32_t plane_bytes = uint32_t(plane * int64_t(sizeof(Real)));
-  const int nxt = (nx + kPlaneTileX - 1) / kPlaneTileX, nzt = (nz + kPlaneTileZ - 1) / kPlaneTileZ;
+  const int nxt = (nx + kPlaneTileX - 1) / kPlaneTileX, nzt = (nz + kTZ - 1) / kTZ;
   const cptr<Real> vtab = as_const(a.vtab);
   const cptr<double> itab = as_const(a.itab);
   const int stage = a.stage;
@@ -226,7 +228,7 @@ void plane_stage_kernel(PlaneArgs<Real> a) {
   for (int v = blockIdx.x; v < nxt * nzt; v += gridDim.x) {
     int xt, zt;
     plane_tile(v, nxt, nzt, xt, zt);
-    const int x0 = xt * kPlaneTileX, z0 = zt * kPlaneTileZ;
+    const int x0 = xt * kPlaneTileX, z0 = zt * kTZ;
     const int x = x0 + tx, z = z0 + tz;
     const bool valid = x < nx && z < nz;
     const int cell = min(z, nz - 1) * ldx + min(x, nx - 1);
@@ -237,7 +239,7 @@ void plane_stage_kernel(PlaneArgs<Real> a) {
     int lslot[kTileLoads];
 #pragma unroll
     for (int q = 0; q < kTileLoads; ++q) {
-      const int e = t + 256 * q;
+      const int e = t + kThreads * q;
       const int r = min(e, kTileElems - 1) / kTileCols, c = min(e, kTileElems - 1) % kTileCols;
       const int gz = min(max(z0 - 3 + r, 0), nz - 1), gx = min(max(x0 - 3 + c, 0), nx - 1);
       loff[q] = uint32_t(gz * ldx + gx) * uint32_t(sizeof(Real));
@@ -309,10 +311,10 @@ void plane_stage_kernel(PlaneArgs<Real> a) {
           const Real* T = L + lane_off;
           L[kFxOff + lane_off] = face<Real, 1>(T + 3 * kLd, ux, eps4);
           L[kFzOff + lane_off] = face<Real, kLd>(T + 3, uz, eps4);
-          const int wz = (int(blockIdx.x) + s) & 3;
+          const int wz = (int(blockIdx.x) + s) & (kTZ - 1);
           if (wave == wz)
-            L[kFzOff + kPlaneTileZ * kLd + tx] = face<Real, kLd>(L + kPlaneTileZ * kLd + 3 + tx, uz, eps4);
-          if (wave == (wz ^ 2) && tx < kPlaneTileZ)
+            L[kFzOff + kTZ * kLd + tx] = face<Real, kLd>(L + kTZ * kLd + 3 + tx, uz, eps4);
+          if (wave == (wz ^ (kTZ / 2)) && tx < kTZ)
             L[kFxOff + tx * kLd + kPlaneTileX] = face<Real, 1>(L + (tx + 3) * kLd + kPlaneTileX, ux, eps4);
           __syncthreads();
           // 4. update
@@ -473,9 +475,9 @@ template <typename Real, int QPT, int NVT>
 hipError_t stage_t(const void* args, int grid, hipStream_t s) {
   const PlaneArgs<Real>& a = *static_cast<const PlaneArgs<Real>*>(args);
   if (a.stage == 1)
-    hipLaunchKernelGGL((plane_stage_kernel<Real, QPT, NVT, false>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((plane_stage_kernel<Real, QPT, NVT, false>), dim3(grid), dim3(kThreads), 0, s, a);
   else
-    hipLaunchKernelGGL((plane_stage_kernel<Real, QPT, NVT, true>), dim3(grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((plane_stage_kernel<Real, QPT, NVT, true>), dim3(grid), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 
@@ -502,6 +504,10 @@ hipError_t init_real(int qpt, int nvt, const void* args, int grid, hipStream_t s
 }
 
 }  // namespace
+
+int plane_stage_grid(int nx, int nz) {
+  return ((nx + kPlaneTileX - 1) / kPlaneTileX) * ((nz + kTZ - 1) / kTZ);
+}
 
 hipError_t launch_plane_stage(int prec_fp32, int qpt, int nvt, const void* args, int grid, hipStream_t stream) {
   return prec_fp32 ? stage_real<float>(qpt, nvt, args, grid, stream) : stage_real<double>(qpt, nvt, args, grid, stream);

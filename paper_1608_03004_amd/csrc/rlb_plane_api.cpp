@@ -34,7 +34,7 @@ struct rlb_plane {
   rlb_precision prec = RLB_FP64;
   size_t rsize = 8;
   PlaneDev pd;
-  int qpt = 3, nvt = 5, grid = 1;
+  int qpt = 3, nvt = 5, grid = 1, stage_grid = 1;
   std::vector<double> vtab_d, itab, aux_d;
   std::vector<float> vtab_f, aux_f;
   int aux_pairs = 0;
@@ -144,7 +144,7 @@ hipError_t plane_stage(rlb_plane* P, int stage, size_t fin, size_t fout, size_t 
   a.fout = P->dev<Real>(fout);
   a.rec_in = P->dev<double>(rin);
   a.rec_out = P->dev<double>(rout);
-  return launch_plane_stage(sizeof(Real) == 4, P->qpt, P->nvt, &a, P->grid, P->stream);
+  return launch_plane_stage(sizeof(Real) == 4, P->qpt, P->nvt, &a, P->stage_grid, P->stream);
 }
 
 template <typename Real>
@@ -267,6 +267,7 @@ rlb_status rlb_plane_create(const rlb_plane_desc* desc, rlb_precision prec, rlb_
   else if (d.n_v <= 5 && d.q_p == 4) { P->qpt = 4; P->nvt = 5; }
   else { P->qpt = 8; P->nvt = 7; }
   P->grid = ((d.nx + kPlaneTileX - 1) / kPlaneTileX) * ((d.nz + kPlaneTileZ - 1) / kPlaneTileZ);
+  P->stage_grid = plane_stage_grid(d.nx, d.nz);
   P->state_elems = int64_t(d.q_p) * d.q_xi * qh * pd.plane;
   // workspace layout
   size_t o = 0;
