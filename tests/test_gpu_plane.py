@@ -67,6 +67,9 @@ CASES = [
     (dict(nx=24, nz=24, q_xi=8, q_phi=10, q_p=4, tau=5e-2), "quadrants"),    # Q_p = 4 group
     (dict(nx=16, nz=20, q_xi=7, q_phi=10, q_p=5, n_p=3, n_v=7, tau=1e-1), "blob"),  # generic group
     (dict(nx=20, nz=18, q_xi=8, q_phi=8, q_p=3, tau=math.inf), "blob"),      # collisionless
+    (dict(nx=8, nz=8, q_xi=6, q_phi=8, q_p=3, tau=1e-2), "quadrants"),       # the smallest plane
+    (dict(nx=9, nz=67, q_xi=7, q_phi=8, q_p=3, tau=2e-2), "blob"),           # thin, odd q_xi, ragged tile rows
+    (dict(nx=130, nz=9, q_xi=6, q_phi=9, q_p=4, tau=5e-3), "quadrants"),     # three tile columns, one row
 ]
 
 
