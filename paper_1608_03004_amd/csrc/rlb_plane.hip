@@ -198,12 +198,14 @@ __device__ inline Real face(const Real* p, bool up, Real eps4) {
 }
 
 // Occupancy: 6 waves per SIMD (three workgroups) for FP32 and 4 for FP64
-// with Q_p <= 4 (the per-cell coefficients of the other radial nodes and a few
-// tile constants spill, outside the point loop); the generic Q_p <= 8 group is
-// left to the compiler.
+// with Q_p <= 4, 4 for FP32 in the generic Q_p <= 8 group (the per-cell
+// coefficients of the other radial nodes and a few tile constants spill,
+// outside the point loop; measured 0.99 against 1.41 ms per step with the
+// compiler's choice on a 512^2 plane with Q_p = 5); the FP64 generic group is
+// left to the compiler (3 waves measured 29 % slower).
 template <typename Real, int QPT>
 constexpr int plane_waves_per_eu() {
-  return QPT > 4 ? 1 : (sizeof(Real) == 4 ? 6 : 4);
+  return QPT > 4 ? (sizeof(Real) == 4 ? 4 : 1) : (sizeof(Real) == 4 ? 6 : 4);
 }
 
 template <typename Real, int QPT, int NVT, bool HAS_FN>
