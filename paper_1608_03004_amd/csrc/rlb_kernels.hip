@@ -171,16 +171,21 @@ struct Moments3 {
 // Waves per SIMD the register allocation must allow.  The first stage of a
 // step (no f^n stream) is limited by its arithmetic, and one more resident
 // wave per SIMD there outweighs the few registers it spills (measured on the
-// Q_p <= 4 groups: +1 % FP32, +2 % FP64 per step); stages 2 and 3 are
-// bandwidth-bound, and the Q_p = 8 group holds too many coefficients, so
-// they keep every value in registers.
-template <typename Real, int QPT, bool HAS_FN>
+// Q_p <= 4 groups: +1 % FP32, +2 % FP64 per step); stages 2 and 3 of those
+// groups are bandwidth-bound and keep every value in registers.  The FP32
+// Q_p <= 8 group runs at 4 waves instead of the compiler's 3 (a 2^19-cell tube
+// with Q = 64 x 5: 1.35 against 1.41 ms per step); its FP64 form keeps all
+// its coefficients in registers (3 waves measured 18 % slower).  The
+// high-order variant (NVT < 0) holds no coefficients and is left to the
+// compiler.
+template <typename Real, int QPT, int NVT, bool HAS_FN>
 constexpr int stage_waves_per_simd() {
-  return (HAS_FN || QPT > 4) ? 1 : (sizeof(Real) == 4 ? 5 : 4);
+  return NVT < 0 ? 1
+                 : QPT > 4 ? (sizeof(Real) == 4 ? 4 : 1) : (HAS_FN ? 1 : (sizeof(Real) == 4 ? 5 : 4));
 }
 
 template <typename Real, int TILE, int QPT, int NVT, bool HAS_FN, int CH>
-__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(stage_waves_per_simd<Real, QPT, HAS_FN>())))
+__global__ __launch_bounds__(TILE) __attribute__((amdgpu_waves_per_eu(stage_waves_per_simd<Real, QPT, NVT, HAS_FN>())))
 void stage_kernel(StageArgs<Real> a) {
   constexpr int V = LdsVec<Real>::V, NH = CH / V;
   static_assert(CH % V == 0, "a chunk is a whole number of 16-byte LDS words");
