@@ -411,13 +411,15 @@ def cpu_baseline(params, target_s=12.0):
     t = O.Tube(nx=nx, q_xi=params["q_xi"], q_p=params["q_p"], tau=params["tau"], dt=0.5 / params["nx"])
     F = O.init(t, SOD_L, SOD_R)
     F = O.step(t, F, 1)  # warm-up (thread pool, first touch of the arrays)
-    t0 = time.perf_counter()
-    F = O.step(t, F, 1)
-    one = time.perf_counter() - t0
-    n = max(1, min(200, int(target_s / max(one, 1e-3))))
-    t0 = time.perf_counter()
-    F = O.step(t, F, n)
-    secs = time.perf_counter() - t0
+    # batches of 1, 2, 4, ... steps until target_s of stepping is timed (the
+    # first steps run slower than the steady state, so no single-step estimate)
+    n, secs, k = 0, 0.0, 1
+    while secs < target_s and n < 400:
+        t0 = time.perf_counter()
+        F = O.step(t, F, k)
+        secs += time.perf_counter() - t0
+        n += k
+        k = min(2 * k, 400 - n)
     return dict(value=nx * t.Q * n / secs, unit="cell*quad-point updates/s", cores=O.num_threads(), kind="oracle",
                 sample=f"FP64 oracle on {nx} cells x Q={t.Q} ({params['q_xi']}x{params['q_p']}), tau={params['tau']}, "
                        f"{n} steps in {secs:.1f} s (the headline tube's per-point work on 1/16 of its cells)")
