@@ -405,7 +405,8 @@ def leg_copy(nbytes=1 << 30, reps=5):
 
 def cpu_baseline(params, target_s=12.0):
     """The CPU FP64 oracle on a bounded sample: the headline tube's Q and tau on
-    a sub-tube of 2^16 cells, timed over whole steps (about 10 s of CPU work)."""
+    a sub-tube of 2^16 cells, timed over whole steps (12 to about 25 s of CPU
+    work)."""
     from oracle import oracle as O
     nx = 1 << 16
     t = O.Tube(nx=nx, q_xi=params["q_xi"], q_p=params["q_p"], tau=params["tau"], dt=0.5 / params["nx"])
