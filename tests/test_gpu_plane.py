@@ -70,6 +70,7 @@ CASES = [
     (dict(nx=8, nz=8, q_xi=6, q_phi=8, q_p=3, tau=1e-2), "quadrants"),       # the smallest plane
     (dict(nx=9, nz=67, q_xi=7, q_phi=8, q_p=3, tau=2e-2), "blob"),           # thin, odd q_xi, ragged tile rows
     (dict(nx=130, nz=9, q_xi=6, q_phi=9, q_p=4, tau=5e-3), "quadrants"),     # three tile columns, one row
+    (dict(nx=12, nz=10, q_xi=64, q_phi=64, q_p=8, n_p=3, n_v=7, tau=1e-2), "blob"),  # Q = 8 x 64 x 33
 ]
 
 
