@@ -54,6 +54,32 @@ def _quadrants(pl):
     return f
 
 
+def _waves(pl):
+    # smooth variations everywhere, so that every window (edges included) has
+    # structure
+    x, z = pl.centres()
+    X, Z = np.meshgrid(x, z)
+    f = np.zeros((4, pl.nz, pl.nx))
+    f[0] = 0.6 + 0.3 * np.sin(6 * math.pi * X) * np.cos(4 * math.pi * Z)
+    f[1] = 0.7 + 0.2 * np.cos(6 * math.pi * X + 1.0) * np.sin(4 * math.pi * Z)
+    f[2] = 0.2 * np.sin(2 * math.pi * (X + Z))
+    f[3] = 0.15 * np.cos(2 * math.pi * (X - Z))
+    return f
+
+
+def _fields_err_tensor_scale(gpu, ref):
+    # error of each component relative to its tensor's scale (N^mu to N^0,
+    # T^{mu nu} and e to T^00, v to the speed of light), for windows where a
+    # component passes through zero
+    scale = {k: np.abs(ref[NAMES.index(k)]).max() for k in ("N0", "T00", "n", "T")}
+    ref_of = {"N0": "N0", "Nx": "N0", "Nz": "N0", "n": "n", "T": "T"}
+    out = {}
+    for k, name in enumerate(NAMES):
+        s = 1.0 if name in ("vx", "vz") else scale[ref_of.get(name, "T00")]
+        out[name] = np.abs(gpu[k] - ref[k]).max() / s
+    return out
+
+
 def _fields_err(gpu, ref):
     out = {}
     for k, name in enumerate(NAMES):
@@ -161,6 +187,31 @@ def test_plane_full_size_window(torch_cuda):
     errs = _fields_err(full, ref)
     print("[plane 1024^2 fp32 window] " + " ".join(f"{k}:{v:.1e}" for k, v in errs.items()), flush=True)
     assert max(errs.values()) < 1e-5, errs
+
+
+def test_plane_max_size_windows(torch_cuda):
+    # the largest plane the library accepts, 8192 x 8192 = 2^26 cells, Q = 120,
+    # FP32 (three states of 32 GB), smooth data: a window at the centre and
+    # one at the upper corner (outflow edges, largest indices) follow the
+    # oracle on windows widened by 9 cells per step inward
+    from oracle import oracle as O
+    from paper_1608_03004_amd import Plane, PlaneSpec
+    n, nsteps, w = 8192, 2, 24
+    pad = 9 * nsteps
+    spec = PlaneSpec(nx=n, nz=n, q_xi=8, q_phi=8, q_p=3, tau=1e-2)
+    gp = Plane(spec, precision="fp32")
+    gp.set_initial_fields(_waves(O.Plane(nx=n, nz=n, q_xi=8, q_phi=8, q_p=3, tau=1e-2)))
+    gp.step(nsteps)
+    d = 1.0 / n
+    for name, (a, b) in (("centre", (n // 2 - w, n // 2 + w)), ("corner", (n - 2 * w, n))):
+        lo, hi = a - pad, min(b + pad, n)
+        full = gp.fields()[:, a:b, a:b].cpu().numpy()
+        win = O.Plane(nx=hi - lo, nz=hi - lo, q_xi=8, q_phi=8, q_p=3, tau=1e-2, x_min=-0.5 + lo * d,
+                      x_max=-0.5 + hi * d, z_min=-0.5 + lo * d, z_max=-0.5 + hi * d, dt=gp.info()["dt"])
+        ref = O.plane_fields(win, O.plane_run(win, _waves(win), nsteps))[:, a - lo:b - lo, a - lo:b - lo]
+        errs = _fields_err_tensor_scale(full, ref)
+        print(f"[plane 8192^2 fp32 {name} window] " + " ".join(f"{k}:{v:.1e}" for k, v in errs.items()), flush=True)
+        assert max(errs.values()) < 1e-5, (name, errs)
 
 
 def test_plane_nonphysical_state_raises_sticky_flag(torch_cuda):
