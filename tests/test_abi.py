@@ -190,3 +190,16 @@ def test_valid_plane_create_and_host_queries(lib):
     assert Q.value == 120 and abs(dt.value - 0.5 / (70 + 13)) < 1e-18
     assert lib.rlb_plane_step(h, 1) == rlb.RLB_ERR_STATE
     assert lib.rlb_plane_destroy(h) == 0
+
+
+def test_missing_library_raises_instead_of_falling_back(monkeypatch, tmp_path):
+    # the product path has no CPU or torch fallback: without librlb.so every
+    # entry point raises
+    monkeypatch.setattr(rlb, "LIB_PATH", str(tmp_path / "librlb.so"))
+    monkeypatch.setattr(rlb, "_lib", None)
+    with pytest.raises(ImportError, match="no non-HIP fallback"):
+        rlb.load_library()
+    with pytest.raises(ImportError):
+        rlb.Lattice([rlb.Tube(nx=64, q_xi=8, q_p=3, tau=1e-2)])
+    with pytest.raises(ImportError):
+        rlb.Plane(rlb.PlaneSpec(nx=16, nz=16))
