@@ -212,6 +212,10 @@ template <typename Real, int QPT, int NVT, bool HAS_FN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(plane_waves_per_eu<Real, QPT>())))
 void plane_stage_kernel(PlaneArgs<Real> a) {
   __shared__ Real lds[2 * kBufElems];
+  // FP64: the nine record sums of each lane live in LDS (registers are the
+  // scarce resource at four waves per SIMD); FP32 keeps them in registers
+  constexpr bool kMomLds = sizeof(Real) == 8;
+  __shared__ double mom_lds[kMomLds ? 9 : 1][kThreads];
   const cptr<PlaneDev> P = as_const(a.pl);
   const int nx = P->nx, nz = P->nz, ldx = P->ldx, qx = P->qx, qh = P->qh, qp = P->qp;
   const int64_t plane = P->plane;
@@ -260,7 +264,14 @@ void plane_stage_kernel(PlaneArgs<Real> a) {
     feq_coefficients<Real, QPT, NVT>(Real(M.n), Real(M.T), Real(M.gamma), Real(ua), Real(P->T0), qp, P->np, P->nv,
                                      itab, as_const(a.aux), a.aux_pairs, D);
     const Real g0 = Real(M.gamma * P->tau_inv), gx = Real(M.ux * P->tau_inv), gz = Real(M.uz * P->tau_inv);
-    double mom[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    double mom[kMomLds ? 1 : 9];
+    if constexpr (kMomLds) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) mom_lds[c][t] = 0.0;
+    } else {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) mom[c] = 0.0;
+    }
     const int Q = qp * qx * qh;
     // first point's tile values
     Real pre[kTileLoads];
@@ -348,11 +359,20 @@ void plane_stage_kernel(PlaneArgs<Real> a) {
       double S[6];
 #pragma unroll
       for (int q = 0; q < 6; ++q) S[q] = acc.S[q].value();
-      add_node9(mom, itab + i * kIStride, S);
+      if constexpr (kMomLds) {
+        double mm[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) mm[c] = mom_lds[c][t];
+        add_node9(mm, itab + i * kIStride, S);
+#pragma unroll
+        for (int c = 0; c < 9; ++c) mom_lds[c][t] = mm[c];
+      } else {
+        add_node9(mom, itab + i * kIStride, S);
+      }
     }
     if (valid) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) a.rec_out[c * plane + cell] = mom[c];
+      for (int c = 0; c < 9; ++c) a.rec_out[c * plane + cell] = kMomLds ? mom_lds[c][t] : mom[c];
     }
     __syncthreads();  // the next tile reuses the LDS buffers
   }
