@@ -20,7 +20,8 @@
  * - Device pointers are plain HIP device addresses.  The caller owns the
  *   workspace (rlb_bind) and every state/adjoint buffer it passes in; the
  *   library owns only the opaque handle and its host-side tables.  The library
- *   never allocates device memory.
+ *   never allocates device memory; its only device memory of its own is the
+ *   static scratch array of rlb_step_noalloc (see there).
  * - Work is queued asynchronously on the HIP stream given to rlb_bind (NULL
  *   means the legacy default stream).  Calls documented as "synchronizes" wait
  *   for that stream.  A lattice must not be used from two threads at once.
@@ -229,6 +230,32 @@ rlb_status rlb_fields_adjoint(rlb_lattice* lat, int32_t tube, const void* state,
                               void* lambda);
 rlb_status rlb_initial_state_adjoint(rlb_lattice* lat, int32_t tube, const void* lambda0, double grad_left[3],
                                      double grad_right[3]);
+
+/*
+ * Allocation-free time steps, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Advances the caller's state (device memory, state layout and
+ * precision of the lattice: input f^n, output f^{n+nsteps}, in place) by
+ * nsteps SSP-RK3 steps with the lattice's tubes, time steps and schedule
+ * (without graph replay), on hip_stream; asynchronous.  The lattice needs no
+ * workspace (rlb_bind is not required) and its own state, time and flag are
+ * not touched.  The moment records are recomputed from `state` first, so the
+ * result equals, bit for bit, rlb_set_state(state) followed by
+ * rlb_step(nsteps) on a bound lattice.
+ * Every other buffer of the step (stage arrays, moment records, tables, work
+ * list, node-split sums, high-order equilibrium values) lives in a static
+ * device array of RLB_NOALLOC_SCRATCH_BYTES per GPU, held from the first call
+ * on a GPU until the process ends; the call makes no allocation.  A lattice
+ * whose step needs more is rejected with RLB_ERR_INVALID_ARG (the reason is
+ * in rlb_last_error).  Calls on one GPU share the array and must not overlap
+ * (they race); consecutive calls on one stream are fine, whatever lattice
+ * they use.
+ * flags_device: NULL, or one device word that receives the sticky flag bits
+ * raised during this call (bit 0: non-physical state, bit 1: |v| > 0.95); it
+ * is cleared at the start of the call.  state must not overlap flags_device.
+ */
+#define RLB_NOALLOC_SCRATCH_BYTES (64u << 20)
+rlb_status rlb_step_noalloc(rlb_lattice* lat, void* state, int64_t nsteps, uint32_t* flags_device, void* hip_stream);
 
 /* Plain device copy kernel (bandwidth calibration); asynchronous. */
 rlb_status rlb_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);

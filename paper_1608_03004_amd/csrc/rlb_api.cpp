@@ -61,6 +61,7 @@ struct rlb_lattice {
   size_t off_part = 0;  // per-node sums of split launches (0: none)
   size_t off_ztab = 0, off_feq = 0;  // high-order tables and equilibrium values (0: none)
   int part_stride = 0;  // doubles per cell in that buffer
+  size_t step_bytes = 0;  // bytes of the layout before f^n (see rlb_create)
   // adjoint workspace (RLB_WITH_ADJOINT)
   int64_t cell_elems = 0, face_elems = 0;
   int init_blocks_max = 0;
@@ -89,8 +90,15 @@ struct rlb_lattice {
   std::vector<int32_t> mask_h;
   std::string err;
 
+  // allocation-free step: the caller's state stands in for f^n and the
+  // caller's word (or the scratch copy) for the flag while it runs
+  void* f0_ext = nullptr;
+  unsigned* flag_ext = nullptr;
+
   template <typename T>
   T* dev(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  void* F(int k) const { return (k == 0 && f0_ext) ? f0_ext : static_cast<void*>(ws + off_F[k]); }
+  unsigned* flag() const { return flag_ext ? flag_ext : dev<unsigned>(off_flag); }
 };
 
 namespace {
@@ -310,7 +318,7 @@ hipError_t stage_group(rlb_lattice* L, const Group& g, int stage, const void* fi
   a.fout = static_cast<Real*>(fout);
   a.rec_in = rec_in;
   a.rec_out = rec_out;
-  a.flag = L->dev<unsigned>(L->off_flag);
+  a.flag = L->flag();
   a.part = ls.nodes > 1 ? L->dev<double>(L->off_part) : nullptr;
   a.part_stride = L->part_stride;
   a.feq = nullptr;
@@ -334,9 +342,9 @@ rlb_status enqueue_steps(rlb_lattice* L, hipStream_t s, int64_t nsteps) {
       const int fout = stage == 1 ? 1 : (stage == 2 ? 2 : 0);
       const int rin = fin, rout = fout;
       for (const Group& g : L->groups) {
-        const void* Fin = L->ws + L->off_F[fin];
-        const void* Fn = L->ws + L->off_F[0];
-        void* Fout = L->ws + L->off_F[fout];
+        const void* Fin = L->F(fin);
+        const void* Fn = L->F(0);
+        void* Fout = L->F(fout);
         const double* Rin = L->dev<double>(L->off_rec[rin]);
         double* Rout = L->dev<double>(L->off_rec[rout]);
         const hipError_t e = fp32 ? stage_group<float>(L, g, stage, Fin, Fn, Fout, Rin, Rout, s)
@@ -563,9 +571,13 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
   for (auto& d : L->desc) max_items += (d.nx + 127) / 128;
   L->max_items = static_cast<int>(max_items);
 
-  // workspace layout
+  // workspace layout: first everything a time step uses besides the state
+  // f^n (the stage arrays, records, tables, flag, buffers), up to
+  // step_bytes, then f^n, then the adjoint's arrays; the allocation-free step
+  // keeps the first part in its static scratch array and takes f^n from the
+  // caller
   size_t o = 0;
-  for (int k = 0; k < 3; ++k) { L->off_F[k] = o; o = align256(o + L->state_elems * L->rsize); }
+  for (int k = 1; k < 3; ++k) { L->off_F[k] = o; o = align256(o + L->state_elems * L->rsize); }
   for (int k = 0; k < 3; ++k) { L->off_rec[k] = o; o = align256(o + L->rec_elems * 8); }
   L->off_tubes = o; o = align256(o + L->tubes.size() * sizeof(TubeDev));
   L->off_jtab = o; o = align256(o + L->jtab_d.size() * L->rsize);
@@ -588,6 +600,8 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
     L->part_stride = 3 * qp_max;
     L->off_part = o; o = align256(o + size_t(L->cell_elems) * L->part_stride * 8);
   }
+  L->step_bytes = o;
+  L->off_F[0] = o; o = align256(o + L->state_elems * L->rsize);
   if (flags & RLB_WITH_ADJOINT) {
     for (int k = 0; k < 2; ++k) { L->off_aF[k] = o; o = align256(o + L->state_elems * L->rsize); }
     for (int k = 0; k < 3; ++k) { L->off_arec[k] = o; o = align256(o + L->rec_elems * 8); }
@@ -1148,6 +1162,78 @@ rlb_status rlb_initial_state_adjoint(rlb_lattice* L, int32_t tube, const void* l
   }
   return RLB_OK;
 }
+
+}  // extern "C"
+
+namespace rlb {
+
+size_t noalloc_scratch_bytes(const rlb_lattice* L) { return L->step_bytes; }
+
+rlb_status noalloc_validate(rlb_lattice* L, const void* state, int64_t nsteps, size_t max_bytes) {
+  if (!L) return RLB_ERR_INVALID_ARG;
+  if (!state) return fail(L, RLB_ERR_INVALID_ARG, "state is NULL");
+  if (reinterpret_cast<uintptr_t>(state) % L->rsize)
+    return fail(L, RLB_ERR_INVALID_ARG, "state must be aligned to its element size");
+  if (nsteps < 0) return fail(L, RLB_ERR_INVALID_ARG, "nsteps must be >= 0");
+  if (L->step_bytes > max_bytes) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf,
+                  "the lattice's step needs %zu bytes of scratch; the allocation-free step holds at most %zu",
+                  L->step_bytes, max_bytes);
+    return fail(L, RLB_ERR_INVALID_ARG, buf);
+  }
+  return RLB_OK;
+}
+
+rlb_status noalloc_hip_error(rlb_lattice* L, hipError_t e, const char* where) { return hip_fail(L, e, where); }
+
+// Time steps of a caller-owned state with every other device buffer of the
+// step (stage arrays, records, tables, work lists, node-split sums, the
+// high-order equilibrium values and, unless the caller passes its own word,
+// the flag) placed in `scratch` at the lattice's workspace offsets.  The
+// lattice's own binding is left as it was.
+rlb_status noalloc_steps(rlb_lattice* L, char* scratch, void* state, unsigned* flag_out, int64_t nsteps,
+                         hipStream_t s) {
+  struct Restore {
+    rlb_lattice* L;
+    char* ws;
+    hipStream_t stream;
+    ~Restore() {
+      L->ws = ws;
+      L->stream = stream;
+      L->f0_ext = nullptr;
+      L->flag_ext = nullptr;
+    }
+  } restore{L, L->ws, L->stream};
+  L->ws = scratch;
+  L->stream = s;
+  L->f0_ext = state;
+  L->flag_ext = flag_out;
+  auto put = [&](size_t off, const void* src, size_t bytes) {
+    return bytes ? hipMemcpyAsync(scratch + off, src, bytes, hipMemcpyHostToDevice, s) : hipSuccess;
+  };
+  const bool fp32 = L->prec == RLB_FP32;
+  HIP_TRY(L, put(L->off_tubes, L->tubes.data(), L->tubes.size() * sizeof(TubeDev)));
+  HIP_TRY(L, fp32 ? put(L->off_jtab, L->jtab_f.data(), L->jtab_f.size() * 4)
+                  : put(L->off_jtab, L->jtab_d.data(), L->jtab_d.size() * 8));
+  HIP_TRY(L, fp32 ? put(L->off_aux, L->aux_f.data(), L->aux_f.size() * 4)
+                  : put(L->off_aux, L->aux_d.data(), L->aux_d.size() * 8));
+  HIP_TRY(L, put(L->off_itab, L->itab.data(), L->itab.size() * 8));
+  HIP_TRY(L, put(L->off_aux_d, L->aux_d.data(), L->aux_d.size() * 8));
+  HIP_TRY(L, put(L->off_items, L->items.data(), L->items.size() * sizeof(WorkItem)));
+  HIP_TRY(L, put(L->off_ztab, L->ztab.data(), L->ztab.size() * 8));
+  // the scratch keeps the previous call's contents: only the flag must start
+  // at zero (a fill kernel, no memset node); every record, stage value and
+  // node sum is written before it is read
+  HIP_TRY(L, launch_fill_u32(L->flag(), 1, 0u, s));
+  rlb_status st = moments_of(L, state, L->dev<double>(L->off_rec[0]));
+  if (st != RLB_OK) return st;
+  return enqueue_steps(L, s, nsteps);
+}
+
+}  // namespace rlb
+
+extern "C" {
 
 rlb_status rlb_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream) {
   if ((!dst || !src) && bytes) return RLB_ERR_INVALID_ARG;

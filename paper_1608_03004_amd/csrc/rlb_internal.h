@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/rlb.h"
+
 namespace rlb {
 
 constexpr int kMaxQp = 8;   // radial (Gauss-Laguerre) order limit
@@ -174,6 +176,7 @@ hipError_t launch_fields(const TubeDev* tubes, int tube, int nx, const double* r
                          unsigned* flag, hipStream_t stream);
 hipError_t launch_totals(const TubeDev* tubes, int tube, const double* rec, double* out, hipStream_t stream);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
+hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t stream);
 hipError_t launch_feq(int prec_fp32, const LaunchShape& ls, const void* args, hipStream_t stream);
 hipError_t launch_combine(const TubeDev* tubes, const WorkItem* items, int nitems, int tile, const double* itab,
                           const double* part, int part_stride, double* rec_out, hipStream_t stream);
@@ -233,5 +236,16 @@ hipError_t launch_initial_adjoint(int prec_fp32, int qpt, int nvt, const TubeDev
                                   const void* jtab, const double* itab, const double* aux_d, int aux_pairs,
                                   const double* sides, const void* lambda0, double* partials, int nblocks_max,
                                   double* grad_out, hipStream_t stream);
+
+// Allocation-free step (rlb_noalloc.hip, host side in rlb_api.cpp): bytes of
+// scratch a lattice's step needs besides its state, and the steps themselves
+// with every such buffer in `scratch` (device memory of at least that size).
+size_t noalloc_scratch_bytes(const rlb_lattice* L);
+// Argument checks of the allocation-free step (reasons go to rlb_last_error)
+// and the report of a HIP error on a lattice.
+rlb_status noalloc_validate(rlb_lattice* L, const void* state, int64_t nsteps, size_t max_bytes);
+rlb_status noalloc_hip_error(rlb_lattice* L, hipError_t e, const char* where);
+rlb_status noalloc_steps(rlb_lattice* L, char* scratch, void* state, unsigned* flag_out, int64_t nsteps,
+                         hipStream_t s);
 
 }  // namespace rlb

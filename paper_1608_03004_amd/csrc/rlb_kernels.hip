@@ -588,6 +588,13 @@ __global__ __launch_bounds__(256) void copy_kernel(uint4* __restrict__ dst, cons
   for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n16; k += stride) dst[k] = src[k];
 }
 
+// Fills n words with v (flags and counters; a kernel rather than a memset so
+// that the clear can sit in captured work).
+__global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, int n, unsigned v) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) p[k] = v;
+}
+
 template <typename Real, int TILE, int QPT, int NVT>
 hipError_t launch_stage_t(const LaunchShape& ls, const void* args, hipStream_t s) {
   const StageArgs<Real>& a = *static_cast<const StageArgs<Real>*>(args);
@@ -679,6 +686,11 @@ hipError_t launch_combine(const TubeDev* tubes, const WorkItem* items, int nitem
                           const double* part, int part_stride, double* rec_out, hipStream_t stream) {
   hipLaunchKernelGGL(combine_kernel, dim3(nitems), dim3(256), 0, stream, tubes, items, nitems, tile, itab, part,
                      part_stride, rec_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t stream) {
+  if (n > 0) hipLaunchKernelGGL(fill_u32_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, p, n, v);
   return hipGetLastError();
 }
 

@@ -98,6 +98,7 @@ _SIGNATURES = {
     "rlb_adjoint_segment": [_VP, _VP, ctypes.c_int32, _VP, ctypes.c_size_t, _VP, _VP],
     "rlb_fields_adjoint": [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_int64, _VP],
     "rlb_initial_state_adjoint": [_VP, ctypes.c_int32, _VP, _DP, _DP],
+    "rlb_step_noalloc": [_VP, _VP, ctypes.c_int64, _VP, _VP],
 }
 _SIGNATURES.update({
     "rlb_plane_defaults": [ctypes.POINTER(PlaneDesc)],
@@ -184,7 +185,7 @@ class Lattice:
     """
 
     def __init__(self, tubes: Sequence[Tube], precision: str = "fp64", adjoint: bool = False,
-                 stream=None, device=None):
+                 stream=None, device=None, bind: bool = True):
         torch = _torch()
         self.lib = load_library()
         self.tubes = list(tubes)
@@ -198,14 +199,15 @@ class Lattice:
             raise RLBError(st, self.lib.rlb_last_error(None).decode())
         self.h = h
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
-        size = ctypes.c_size_t()
-        self._check(self.lib.rlb_workspace_size(self.h, ctypes.byref(size)))
-        # +256 so that the base can be aligned
-        self._ws = torch.empty(size.value + 256, dtype=torch.uint8, device=self.device)
-        base = self._ws.data_ptr()
-        self._ws_ptr = (base + 255) // 256 * 256
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self._check(self.lib.rlb_bind(self.h, _VP(self._ws_ptr), size.value, _VP(self.stream.cuda_stream)))
+        if bind:
+            size = ctypes.c_size_t()
+            self._check(self.lib.rlb_workspace_size(self.h, ctypes.byref(size)))
+            # +256 so that the base can be aligned
+            self._ws = torch.empty(size.value + 256, dtype=torch.uint8, device=self.device)
+            base = self._ws.data_ptr()
+            self._ws_ptr = (base + 255) // 256 * 256
+            self._check(self.lib.rlb_bind(self.h, _VP(self._ws_ptr), size.value, _VP(self.stream.cuda_stream)))
         n = ctypes.c_int64()
         self._check(self.lib.rlb_state_elems(self.h, ctypes.byref(n)))
         self.state_elems = n.value
@@ -320,6 +322,18 @@ class Lattice:
         state = torch.zeros(self.state_elems, dtype=self.dtype, device=self.device) if state is None else state
         self.tube_view(state, tube).copy_(torch.as_tensor(F, dtype=self.dtype))
         return state
+
+    def step_noalloc(self, state, nsteps: int = 1, flags=None, stream=None):
+        """Advances a caller-owned state tensor in place by nsteps steps with no
+        allocation (rlb_step_noalloc); works on a lattice created with
+        bind=False.  flags: None or a device int32 tensor of one element that
+        receives the sticky flag bits raised during the call."""
+        assert state.dtype == self.dtype and state.is_contiguous() and state.numel() >= self.state_elems
+        fp = _VP(flags.data_ptr()) if flags is not None else None
+        if flags is not None:
+            assert flags.element_size() == 4 and flags.numel() >= 1 and flags.device == state.device
+        s = stream if stream is not None else self.stream
+        self._check(self.lib.rlb_step_noalloc(self.h, _VP(state.data_ptr()), int(nsteps), fp, _VP(s.cuda_stream)))
 
     def set_tau(self, tau: float, tube: int = 0):
         self._check(self.lib.rlb_set_tau(self.h, tube, float(tau)))

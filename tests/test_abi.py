@@ -94,6 +94,25 @@ def test_valid_create_and_host_queries(lib):
     assert lib.rlb_destroy(h) == 0
 
 
+def test_noalloc_step_rejects_bad_arguments_on_the_host(lib):
+    # argument and size checks of the allocation-free step happen before any
+    # device work (no GPU here: nothing is launched, the pointers are never
+    # dereferenced)
+    st, h = _create(lib, [rlb.Tube(nx=1 << 20, q_xi=64, q_p=4)], prec=rlb.RLB_FP32)
+    assert st == 0
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.rlb_step_noalloc(h, fake, 1, None, None) == rlb.RLB_ERR_INVALID_ARG
+    assert b"scratch" in lib.rlb_last_error(h)
+    lib.rlb_destroy(h)
+    st, h = _create(lib, [rlb.Tube(nx=800)])
+    assert st == 0
+    assert lib.rlb_step_noalloc(h, None, 1, None, None) == rlb.RLB_ERR_INVALID_ARG
+    assert lib.rlb_step_noalloc(h, ctypes.c_void_p((1 << 20) + 4), 1, None, None) == rlb.RLB_ERR_INVALID_ARG
+    assert lib.rlb_step_noalloc(h, fake, -1, None, None) == rlb.RLB_ERR_INVALID_ARG
+    assert lib.rlb_step_noalloc(None, fake, 1, None, None) == rlb.RLB_ERR_INVALID_ARG
+    lib.rlb_destroy(h)
+
+
 def test_high_order_tubes_create_without_adjoint(lib):
     # 7 < n_v < q_xi <= 64: the matrix-core equilibrium form; it adds one
     # state-sized equilibrium buffer to the workspace and has no adjoint
