@@ -86,7 +86,8 @@ typedef enum { RLB_FP64 = 0, RLB_FP32 = 1 } rlb_precision;
  *                (CFL with the speed of light, section Numerical results);
  *   T0        -- reference temperature of eq. feq (results do not depend on
  *                it in exact arithmetic);
- *   weno_eps  -- WENO5 epsilon applied to the weight-free F.
+ *   weno_eps  -- WENO5 epsilon applied to the weight-free F; in
+ *                [1e-40, 1e30] for FP32 lattices, [1e-300, 1e30] for FP64.
  * rlb_tube_defaults() fills the paper's values (nx 800, q_xi 8, q_p 3,
  * n_v 5, n_p 2, tau 1e-2, z in [-0.5, 0.5], cfl 0.5, dt_tau_max 0.5, T0 1,
  * weno_eps 1e-6).
@@ -123,7 +124,12 @@ typedef struct rlb_lattice rlb_lattice;
 
 rlb_status rlb_tube_defaults(rlb_tube_desc* desc);
 
-/* Validates the tubes and builds the host tables; no device work.
+/* Validates the tubes and builds the host tables; no device work.  The
+ * tables are the momentum quadrature of the section "Discretization of the
+ * momentum space": Gauss-Legendre nodes and weights in xi = cos(theta)
+ * (eq. polarInt, with the weight 2(1 - xi^2)/((Q+1)^2 P_{Q+1}(xi)^2)) and
+ * Gauss-Laguerre (alpha = 1) nodes and weights in p (the radial rule of the
+ * same section); the grid and time step follow section Numerical results.
  * tubes: ntubes >= 1 descriptors (copied).  prec: arithmetic of the
  * distribution (the Landau matching and the moment records are always FP64).
  * flags: RLB_WITH_ADJOINT or 0 (RLB_WITH_ADJOINT with a tube of n_v > 7 is
@@ -151,20 +157,41 @@ rlb_status rlb_set_initial_state(rlb_lattice* lat, int32_t tube, rlb_state left,
  * (ntubes must equal the lattice's tube count). */
 rlb_status rlb_set_initial_states(rlb_lattice* lat, int32_t ntubes, const rlb_state* left, const rlb_state* right);
 
-/* Advances every tube by nsteps full SSP-RK3 steps (3 stage launches each).
- * Asynchronous. */
+/* Advances every tube by nsteps time steps of eq. Boltz (advection with the
+ * fifth-order WENO scheme and Anderson-Witting relaxation towards the
+ * truncated equilibrium of eq. feqtrunc in the Landau frame) with the
+ * third-order Runge-Kutta integrator of section Numerical results (three
+ * stage launches per step; the moments, Landau frame and equilibrium are
+ * recomputed at every stage).  Asynchronous. */
 rlb_status rlb_step(rlb_lattice* lat, int64_t nsteps);
 
 /* Per-cell fields of one tube, FP64, 10 rows of ld >= nx:
- * N0, Nz, T00, T0z, Tzz, e, n, v, T, |N| = sqrt(N0^2 - Nz^2).
+ * N0, Nz, T00, T0z, Tzz, e, n, v, T, |N| = sqrt(N0^2 - Nz^2): the moments
+ * N^mu and T^{mu nu} as quadrature sums (section Relativistic LB equation,
+ * the definitions of N^mu and T^{mu nu}), the Landau-frame energy density,
+ * density, velocity and temperature (T^mu_nu u^nu = -e u^mu, n = -u_mu N^mu,
+ * e = 3nT), and |N|, the density of the free-streaming profile eq. ballistic.
  * rlb_fields writes a device buffer asynchronously; rlb_moments writes a host
  * buffer, synchronizes, and reports the sticky flag. */
 rlb_status rlb_fields(rlb_lattice* lat, int32_t tube, double* dev_out, int64_t ld);
 rlb_status rlb_moments(rlb_lattice* lat, int32_t tube, double* host_out, int64_t ld);
-/* FP64 totals dz*sum(N0), dz*sum(T00), dz*sum(T0z); synchronizes. */
+/* FP64 totals dz*sum(N0), dz*sum(T00), dz*sum(T0z) -- the integrals of N^0
+ * and T^{0 mu} that the method conserves (section Relativistic LB equation:
+ * the collision term conserves N^mu and T^{mu nu} in the Landau frame) up to
+ * the boundary fluxes; synchronizes. */
 rlb_status rlb_totals(rlb_lattice* lat, int32_t tube, double out[3]);
 /* Synchronizes and reports the sticky flag; RLB_OK if clear. */
 rlb_status rlb_check(rlb_lattice* lat);
+/* Sticky flag bits (rlb_flags, rlb_plane_flags, rlb_step_noalloc). */
+#define RLB_FLAG_NONPHYSICAL 1u /* e <= 0, n <= 0, |v| >= 1 or NaN met          */
+#define RLB_FLAG_FAST_FLOW 2u   /* |v| > 0.95 met: the projection of the
+                                   equilibrium (auxiliary Gauss-Legendre rule of
+                                   48 points in FP64, 24 in FP32) loses accuracy
+                                   there (about 1e-6 relative at |v| = 0.99 in
+                                   FP64); results are still computed */
+/* Synchronizes and returns in *flags every sticky bit raised since the last
+ * initial state (the non-physical bit also makes rlb_check fail). */
+rlb_status rlb_flags(rlb_lattice* lat, uint32_t* flags);
 
 /* State buffers: element count of a full state and each tube's placement. */
 rlb_status rlb_state_elems(const rlb_lattice* lat, int64_t* elems);
@@ -186,8 +213,11 @@ rlb_status rlb_set_state(rlb_lattice* lat, const void* src_device);
  * RLB_ERR_STATE without a bound workspace and a state. */
 rlb_status rlb_equilibrium(rlb_lattice* lat, void* dst_device);
 
-/* Per-tube parameters and time. */
+/* Per-tube parameters and time.  rlb_set_time sets the elapsed time that
+ * rlb_tube_info reports (tube = -1: every tube), e.g. after restoring a saved
+ * state with rlb_set_state, which leaves the clocks as they are. */
 rlb_status rlb_set_tau(rlb_lattice* lat, int32_t tube, double tau);
+rlb_status rlb_set_time(rlb_lattice* lat, int32_t tube, double time);
 rlb_status rlb_tube_info(const rlb_lattice* lat, int32_t tube, double* dt, double* time, int32_t* Q);
 
 /* Quadrature tables of a tube as used on the device (host copies):
@@ -337,6 +367,8 @@ rlb_status rlb_plane_set_state(rlb_plane* pl, const void* src_device);
 rlb_status rlb_plane_info(const rlb_plane* pl, double* dt, double* time, int32_t* Q);
 /* Synchronizes and reports the sticky non-physical flag. */
 rlb_status rlb_plane_check(rlb_plane* pl);
+/* Synchronizes and returns the sticky flag bits (RLB_FLAG_*). */
+rlb_status rlb_plane_flags(rlb_plane* pl, uint32_t* flags);
 const char* rlb_plane_last_error(const rlb_plane* pl);
 
 #ifdef __cplusplus

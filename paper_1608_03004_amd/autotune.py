@@ -3,7 +3,8 @@
 For a lattice it times a few time steps under each candidate schedule
 (cells per workgroup, plain or persistent grid with a number of resident
 workgroups per CU, hipGraph replay of several steps) and keeps the fastest.
-The lattice state is saved before the sweep and restored afterwards.  Results
+The lattice state and the tubes' clocks are saved before the sweep and
+restored afterwards.  Results
 are cached in a JSON file keyed by the device name, the precision and a
 signature of the tube set, so a later run with the same workload reuses the
 choice without timing.
@@ -54,6 +55,7 @@ def tune(lat, steps: int = 4, candidates=CANDIDATES, cache_path: str = DEFAULT_C
         lat.set_schedule(**best)
         return best, cache[key].get("timings", {})
     saved = lat.get_state().clone()
+    clocks = [lat.info(t)["time"] for t in range(len(lat.tubes))]
     timings = {}
     for cand in candidates:
         lat.set_schedule(**cand)
@@ -73,6 +75,8 @@ def tune(lat, steps: int = 4, candidates=CANDIDATES, cache_path: str = DEFAULT_C
     best = json.loads(best_key)
     lat.set_schedule(**best)
     lat.set_state(saved)
+    for t, clock in enumerate(clocks):
+        lat.set_time(clock, t)
     lat.check()
     if use_cache:
         cache = _load(cache_path)

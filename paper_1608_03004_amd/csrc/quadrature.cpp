@@ -22,7 +22,10 @@ typedef long double E;
 
 // Eigenvalues of the symmetric tridiagonal matrix with diagonal d and
 // off-diagonal e (e[k] couples k and k+1), by implicit QL with Wilkinson
-// shifts.  d is overwritten with the eigenvalues (unsorted).
+// shifts.  d is overwritten with the eigenvalues (unsorted).  The iteration is
+// the published tridiagonal QL algorithm (Bowdler, Martin, Reinsch and
+// Wilkinson, Numer. Math. 11 (1968) 293, the "tql1" procedure, also in the
+// public-domain EISPACK library), restated here for extended precision.
 bool tridiagonal_eigenvalues(std::vector<E>& d, std::vector<E> e) {
   const int n = static_cast<int>(d.size());
   e.push_back(0);

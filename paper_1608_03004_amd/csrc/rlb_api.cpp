@@ -196,7 +196,7 @@ rlb_status validate(const rlb_tube_desc& d, int k, std::string& msg) {
   if (!(d.z_max > d.z_min) || !std::isfinite(d.z_min) || !std::isfinite(d.z_max)) return bad("need z_min < z_max");
   if (!(d.tau > 0)) return bad("tau must be > 0 (+inf allowed)");
   if (!(d.T0 > 0) || !std::isfinite(d.T0)) return bad("T0 must be > 0");
-  if (!(d.weno_eps > 0)) return bad("weno_eps must be > 0");
+  if (!(d.weno_eps > 0) || !std::isfinite(d.weno_eps)) return bad("weno_eps must be > 0 and finite");
   if (d.dt < 0 || !std::isfinite(d.dt)) return bad("dt must be >= 0");
   if (d.dt == 0 && !(d.cfl > 0 && std::isfinite(d.cfl))) return bad("cfl must be > 0");
   if (d.dt == 0 && !(d.dt_tau_max > 0)) return bad("dt_tau_max must be > 0");
@@ -440,6 +440,9 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
     std::string msg;
     rlb_status st = validate(tubes[k], k, msg);
     if (st != RLB_OK) return fail(nullptr, st, msg);
+    if (!rlb::weno_eps_in_range(tubes[k].weno_eps, prec == RLB_FP32))
+      return fail(nullptr, RLB_ERR_INVALID_ARG,
+                  "tube " + std::to_string(k) + ": weno_eps must lie in [1e-40, 1e30] (FP32) or [1e-300, 1e30] (FP64)");
     if ((flags & RLB_WITH_ADJOINT) && tubes[k].n_v > kMaxNv)
       return fail(nullptr, RLB_ERR_INVALID_ARG, "the adjoint supports n_v <= 7 only");
   }
@@ -863,6 +866,17 @@ rlb_status rlb_check(rlb_lattice* L) {
   return read_flag(L);
 }
 
+rlb_status rlb_flags(rlb_lattice* L, uint32_t* flags) {
+  rlb_status st = need_ready(L, false);
+  if (st != RLB_OK) return st;
+  if (!flags) return fail(L, RLB_ERR_INVALID_ARG, "flags is NULL");
+  unsigned flag = 0;
+  HIP_TRY(L, hipMemcpyAsync(&flag, L->ws + L->off_flag, sizeof flag, hipMemcpyDeviceToHost, L->stream));
+  HIP_TRY(L, hipStreamSynchronize(L->stream));
+  *flags = flag;
+  return RLB_OK;
+}
+
 rlb_status rlb_state_elems(const rlb_lattice* L, int64_t* elems) {
   if (!L || !elems) return RLB_ERR_INVALID_ARG;
   *elems = L->state_elems;
@@ -926,6 +940,14 @@ rlb_status rlb_set_tau(rlb_lattice* L, int32_t tube, double tau) {
   L->desc[tube].tau = tau;
   L->tubes[tube].tau_inv = 1.0 / tau;
   if (L->ws) return upload(L, L->off_tubes + tube * sizeof(TubeDev), &L->tubes[tube], sizeof(TubeDev));
+  return RLB_OK;
+}
+
+rlb_status rlb_set_time(rlb_lattice* L, int32_t tube, double time) {
+  if (!L || (tube != -1 && !check_tube(L, tube))) return RLB_ERR_INVALID_ARG;
+  if (!std::isfinite(time)) return fail(L, RLB_ERR_INVALID_ARG, "time must be finite");
+  for (int t = 0; t < L->ntubes; ++t)
+    if (tube == -1 || t == tube) L->time[t] = time;
   return RLB_OK;
 }
 

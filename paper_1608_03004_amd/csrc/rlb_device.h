@@ -230,11 +230,22 @@ __device__ inline void feq_coefficients(Real n, Real T, Real gamma, Real u, Real
 // reciprocal remains; eps4 = 4 eps) and by 10/6:
 //   H = v3 + (w0 P0/6 + w1 P1 + w2 P2/2) / (w0 + 6 w1 + 3 w2),
 //   w0 = e1^2 e2^2, w1 = e0^2 e2^2, w2 = e0^2 e1^2,  e_r = 4 (eps + beta_r).
+// The products are fourth powers of the e_r: when the denominator comes out
+// zero, subnormal, infinite or NaN (in FP32: e_r below ~1e-10 on smooth data,
+// e.g. eps <= 1e-12, or above ~1e9, e.g. eps >= 1e9 or huge jumps) the lanes
+// concerned take the weights in the form w_r = (min_s e_s / e_r)^2 instead,
+// which lie in (0, 1] with at least one equal to 1 and cannot under- or
+// overflow (three exact divisions, off the common path).
 __device__ inline float weno_recip(float num, float den) { return num * __builtin_amdgcn_rcpf(den); }
 __device__ inline double weno_recip(double num, double den) {
   double r = __builtin_amdgcn_rcp(den);
   r = fma(r, fma(-den, r, 1.0), r);
   return num * r;
+}
+// positive normal number (one class test)
+template <typename Real>
+__device__ inline bool weno_den_ok(Real den) {
+  return __builtin_isfpclass(den, 0x100);
 }
 
 template <typename Real>
@@ -253,7 +264,11 @@ __device__ inline Real weno5(Real v1, Real v2, Real v3, Real v4, Real v5, Real e
   const Real R2 = Real(1.5) * c - Real(0.5) * t2;         // P2 / 2
   const Real num = w0 * R0 + w1 * R1 + w2 * R2;
   const Real den = w0 + Real(6) * w1 + Real(3) * w2;
-  return v3 + weno_recip(num, den);
+  if (__builtin_expect(weno_den_ok(den), 1)) return v3 + weno_recip(num, den);
+  const Real m = fmin(e0, fmin(e1, e2));
+  const Real q0 = m / e0, q1 = m / e1, q2 = m / e2;
+  const Real x0 = q0 * q0, x1 = q1 * q1, x2 = q2 * q2;
+  return v3 + (x0 * R0 + x1 * R1 + x2 * R2) / (x0 + Real(6) * x1 + Real(3) * x2);
 }
 
 // ---------------------------------------------------------------------------
@@ -382,7 +397,11 @@ __device__ inline void weno5_grad(Real v1, Real v2, Real v3, Real v4, Real v5, R
   const Real e0 = eps + c13 * t0 * t0 + c14 * s0 * s0;
   const Real e1 = eps + c13 * t1 * t1 + c14 * s1 * s1;
   const Real e2 = eps + c13 * t2 * t2 + c14 * s2 * s2;
-  const Real a0 = Real(0.1) / (e0 * e0), a1 = Real(0.6) / (e1 * e1), a2 = Real(0.3) / (e2 * e2);
+  // alpha_r = d_r / e_r^2 scaled by min_s e_s^2 (the weights are unchanged;
+  // no under- or overflow for any positive eps)
+  const Real em = fmin(e0, fmin(e1, e2));
+  const Real r0 = em / e0, r1 = em / e1, r2 = em / e2;
+  const Real a0 = Real(0.1) * r0 * r0, a1 = Real(0.6) * r1 * r1, a2 = Real(0.3) * r2 * r2;
   const Real sa = a0 + a1 + a2;
   const Real w0 = a0 / sa, w1 = a1 / sa, w2 = a2 / sa;
   const Real H = w0 * q0 + w1 * q1 + w2 * q2;

@@ -46,9 +46,17 @@ constexpr int high_aux_pairs(int nv) { return 4 * ((nv + kHighExactMargin + 15) 
 // rows of Ze, Zo: ceil(q_xi / 2) rounded up to the MFMA's M = 16 (zero rows)
 constexpr int high_rows(int qx) { return 16 * (((qx + 1) / 2 + 15) / 16); }
 
+// Range of the WENO5 epsilon: 4 eps must be a positive number of the lattice's
+// precision with room to spare, and e_r = 4 (eps + beta_r) finite.
+inline bool weno_eps_in_range(double eps, bool fp32) {
+  return eps >= (fp32 ? 1e-40 : 1e-300) && eps <= 1e30;
+}
+
 // Sticky device flags.
 constexpr unsigned kFlagNonphysical = 1u;
 constexpr unsigned kFlagFastFlow = 2u;  // |v| > 0.95: projection rule less accurate
+static_assert(kFlagNonphysical == RLB_FLAG_NONPHYSICAL && kFlagFastFlow == RLB_FLAG_FAST_FLOW,
+              "device flag bits are the interface's");
 
 struct TubeDev {
   int64_t f_off;    // element offset of the tube in a state array

@@ -247,11 +247,10 @@ void stage_kernel(StageArgs<Real> a) {
     if constexpr (!kHigh)
       feq_coefficients<Real, QPT, NVT>(Real(M.n), Real(M.T), Real(M.gamma), Real(M.u), Real(tbp->T0), qp, tbp->np,
                                        tbp->nv, itab, as_const(a.aux), a.aux_pairs, D);
-    // out = cn f^n + cs f_in + cs dt L,  L = -xi/dz (F_+ - F_-) - (gamma - xi u)/tau (f - f^eq)
+    // out = (1 - cs) f^n + cs (f_in + dt L),  L = -xi/dz (F_+ - F_-) - (gamma - xi u)/tau (f - f^eq)
     const int stage = a.stage;
-    const Real cn = stage == 1 ? Real(0) : (stage == 2 ? Real(0.75) : Real(1.0 / 3.0));
     const Real cs = stage == 1 ? Real(1) : (stage == 2 ? Real(0.25) : Real(2.0 / 3.0));
-    const Real dt = Real(tbp->dt), dz_inv = Real(tbp->dz_inv), cdt = cs * dt;
+    const Real dt = Real(tbp->dt), dz_inv = Real(tbp->dz_inv);
     const Real g0 = Real(M.gamma * tbp->tau_inv), g1 = Real(M.u * tbp->tau_inv);
     const Real eps4 = Real(4.0 * tbp->weno_eps);
 
@@ -368,9 +367,12 @@ void stage_kernel(StageArgs<Real> a) {
               const Real adv = (wr[e] - wl[e]) * (-J[0] * dz_inv);
               const Real rate = g0 - J[0] * g1;
               const Real L = adv - rate * df;
-              // the RK combination of the stage input and f^n is formed first,
-              // so that a state with L = 0 is reproduced exactly
-              const Real out = HAS_FN ? cdt * L + (cs * fr + cn * nr[c]) : fr + dt * L;
+              // the RK combination as f^n + cs ((f_in - f^n) + dt L): the
+              // difference of two successive stage values is exact, the
+              // small increment carries its own rounding and f^n is added
+              // last, so only the final sum rounds at the scale of F (and a
+              // state with L = 0 is reproduced exactly)
+              const Real out = HAS_FN ? nr[c] + cs * ((fr - nr[c]) + dt * L) : fr + dt * L;
               if (valid) BufIO<Real>::template store<kStoreAux>(out, orow.r, vx, uint32_t(c) * row_bytes);
               p0 += J[1] * out;
               p1 += J[2] * out;

@@ -224,9 +224,8 @@ void plane_stage_kernel(PlaneArgs<Real> a) {
   const cptr<Real> vtab = as_const(a.vtab);
   const cptr<double> itab = as_const(a.itab);
   const int stage = a.stage;
-  const Real cn = stage == 1 ? Real(0) : (stage == 2 ? Real(0.75) : Real(1.0 / 3.0));
   const Real cs = stage == 1 ? Real(1) : (stage == 2 ? Real(0.25) : Real(2.0 / 3.0));
-  const Real dt = Real(P->dt), cdt = cs * dt, dx_inv = Real(P->dx_inv), dz_inv = Real(P->dz_inv);
+  const Real dt = Real(P->dt), dx_inv = Real(P->dx_inv), dz_inv = Real(P->dz_inv);
   const Real eps4 = Real(4.0 * P->weno_eps);
   const int t = threadIdx.x, tx = t % kPlaneTileX, tz = t / kPlaneTileX;
   const int lane_off = tz * kLd + tx;
@@ -338,7 +337,8 @@ void plane_stage_kernel(PlaneArgs<Real> a) {
           const Real adv = (hxr - hxl) * (-vx * dx_inv) + (hzr - hzl) * (-vz * dz_inv);
           const Real rate = g0 - vx * gx - vz * gz;
           const Real Lr = adv - rate * (fr - feq);
-          const Real out = HAS_FN ? cdt * Lr + (cs * fr + cn * fnv) : fr + dt * Lr;
+          // f^n + cs ((f_in - f^n) + dt L): one rounding at the scale of F
+          const Real out = HAS_FN ? fnv + cs * ((fr - fnv) + dt * Lr) : fr + dt * Lr;
           if (valid)
             BufIO<Real>::template store<2>(out, make_rsrc(a.fout + int64_t(s) * plane, plane_bytes), cell_b, 0);
           add_point(p6, V, out);

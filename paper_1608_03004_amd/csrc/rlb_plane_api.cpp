@@ -96,7 +96,7 @@ rlb_status validate_plane(const rlb_plane_desc& d, std::string& msg) {
     return bad("need x_min < x_max and z_min < z_max");
   if (!(d.tau > 0)) return bad("tau must be > 0 (+inf allowed)");
   if (!(d.T0 > 0) || !std::isfinite(d.T0)) return bad("T0 must be > 0");
-  if (!(d.weno_eps > 0)) return bad("weno_eps must be > 0");
+  if (!(d.weno_eps > 0) || !std::isfinite(d.weno_eps)) return bad("weno_eps must be > 0 and finite");
   if (d.dt < 0 || !std::isfinite(d.dt)) return bad("dt must be >= 0");
   if (d.dt == 0 && !(d.cfl > 0 && std::isfinite(d.cfl))) return bad("cfl must be > 0");
   if (d.dt == 0 && !(d.dt_tau_max > 0)) return bad("dt_tau_max must be > 0");
@@ -198,6 +198,8 @@ rlb_status rlb_plane_create(const rlb_plane_desc* desc, rlb_precision prec, rlb_
   std::string msg;
   const rlb_status st = validate_plane(*desc, msg);
   if (st != RLB_OK) return pfail(nullptr, st, msg);
+  if (!rlb::weno_eps_in_range(desc->weno_eps, prec == RLB_FP32))
+    return pfail(nullptr, RLB_ERR_INVALID_ARG, "weno_eps must lie in [1e-40, 1e30] (FP32) or [1e-300, 1e30] (FP64)");
   const rlb_plane_desc& d = *desc;
   std::vector<double> xi, wxi, p, wp;
   if (!gauss_legendre_rule(d.q_xi, xi, wxi) || !gauss_laguerre1_rule(d.q_p, p, wp))
@@ -401,6 +403,17 @@ rlb_status rlb_plane_check(rlb_plane* P) {
   PHIP_TRY(P, hipStreamSynchronize(P->stream));
   if (flag & kFlagNonphysical)
     return pfail(P, RLB_ERR_NONPHYSICAL, "a cell reached a non-physical state (e <= 0, n <= 0, |v| >= 1 or NaN)");
+  return RLB_OK;
+}
+
+rlb_status rlb_plane_flags(rlb_plane* P, uint32_t* flags) {
+  rlb_status st = ready(P, false);
+  if (st != RLB_OK) return st;
+  if (!flags) return pfail(P, RLB_ERR_INVALID_ARG, "flags is NULL");
+  unsigned flag = 0;
+  PHIP_TRY(P, hipMemcpyAsync(&flag, P->ws + P->off_flag, sizeof flag, hipMemcpyDeviceToHost, P->stream));
+  PHIP_TRY(P, hipStreamSynchronize(P->stream));
+  *flags = flag;
   return RLB_OK;
 }
 

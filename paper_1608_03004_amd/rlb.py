@@ -26,6 +26,8 @@ RLB_ERR_UNSTABLE_DT = -5
 RLB_FP64 = 0
 RLB_FP32 = 1
 RLB_WITH_ADJOINT = 1
+RLB_FLAG_NONPHYSICAL = 1
+RLB_FLAG_FAST_FLOW = 2
 
 FIELD_NAMES = ("N0", "Nz", "T00", "T0z", "Tzz", "e", "n", "v", "T", "Nabs")
 
@@ -99,6 +101,8 @@ _SIGNATURES = {
     "rlb_fields_adjoint": [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_int64, _VP],
     "rlb_initial_state_adjoint": [_VP, ctypes.c_int32, _VP, _DP, _DP],
     "rlb_step_noalloc": [_VP, _VP, ctypes.c_int64, _VP, _VP],
+    "rlb_flags": [_VP, ctypes.POINTER(ctypes.c_uint32)],
+    "rlb_set_time": [_VP, ctypes.c_int32, ctypes.c_double],
 }
 _SIGNATURES.update({
     "rlb_plane_defaults": [ctypes.POINTER(PlaneDesc)],
@@ -114,6 +118,7 @@ _SIGNATURES.update({
     "rlb_plane_set_state": [_VP, _VP],
     "rlb_plane_info": [_VP, _DP, _DP, ctypes.POINTER(ctypes.c_int32)],
     "rlb_plane_check": [_VP],
+    "rlb_plane_flags": [_VP, ctypes.POINTER(ctypes.c_uint32)],
 })
 _STRING_FUNCS = {"rlb_status_string": [ctypes.c_int], "rlb_last_error": [_VP], "rlb_plane_last_error": [_VP]}
 
@@ -273,6 +278,12 @@ class Lattice:
     def check(self):
         self._check(self.lib.rlb_check(self.h))
 
+    def flags(self) -> dict:
+        """Sticky flag bits since the last initial state (synchronizes)."""
+        f = ctypes.c_uint32()
+        self._check(self.lib.rlb_flags(self.h, ctypes.byref(f)))
+        return dict(nonphysical=bool(f.value & RLB_FLAG_NONPHYSICAL), fast_flow=bool(f.value & RLB_FLAG_FAST_FLOW))
+
     def layout(self, tube: int):
         off, ld = ctypes.c_int64(), ctypes.c_int64()
         self._check(self.lib.rlb_state_layout(self.h, tube, ctypes.byref(off), ctypes.byref(ld)))
@@ -342,6 +353,9 @@ class Lattice:
         dt, time, Q = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
         self._check(self.lib.rlb_tube_info(self.h, tube, ctypes.byref(dt), ctypes.byref(time), ctypes.byref(Q)))
         return dict(dt=dt.value, time=time.value, Q=Q.value)
+
+    def set_time(self, time: float, tube: int = -1):
+        self._check(self.lib.rlb_set_time(self.h, int(tube), float(time)))
 
     def tables(self, tube: int = 0):
         t = self.tubes[tube]
@@ -546,3 +560,8 @@ class Plane:
 
     def check(self):
         self._check(self.lib.rlb_plane_check(self.h))
+
+    def flags(self) -> dict:
+        f = ctypes.c_uint32()
+        self._check(self.lib.rlb_plane_flags(self.h, ctypes.byref(f)))
+        return dict(nonphysical=bool(f.value & RLB_FLAG_NONPHYSICAL), fast_flow=bool(f.value & RLB_FLAG_FAST_FLOW))

@@ -113,6 +113,17 @@ def test_noalloc_step_rejects_bad_arguments_on_the_host(lib):
     lib.rlb_destroy(h)
 
 
+@pytest.mark.parametrize("eps,prec", [(1e-41, rlb.RLB_FP32), (1e31, rlb.RLB_FP64), (math.inf, rlb.RLB_FP64),
+                                      (1e-301, rlb.RLB_FP64)])
+def test_weno_epsilon_outside_its_range_is_rejected(lib, eps, prec):
+    st, h = _create(lib, [rlb.Tube(nx=64, weno_eps=eps)], prec=prec)
+    assert st == rlb.RLB_ERR_INVALID_ARG and not h.value
+    assert b"weno_eps" in lib.rlb_last_error(None)
+    pd = rlb.PlaneSpec(weno_eps=eps).c()
+    ph = ctypes.c_void_p()
+    assert lib.rlb_plane_create(ctypes.byref(pd), prec, ctypes.byref(ph)) == rlb.RLB_ERR_INVALID_ARG
+
+
 def test_high_order_tubes_create_without_adjoint(lib):
     # 7 < n_v < q_xi <= 64: the matrix-core equilibrium form; it adds one
     # state-sized equilibrium buffer to the workspace and has no adjoint

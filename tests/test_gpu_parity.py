@@ -241,15 +241,55 @@ def test_nonphysical_state_raises_sticky_flag(torch_cuda):
     lat.check()
 
 
-def _window_check(params, precision, nsteps, half=256, tol=1e-12):
-    """Full-size run on the GPU; the oracle follows a window around z = 0."""
+def _side_fields(params, state):
+    """Fields of a uniform side state under the tube's quadrature (oracle)."""
+    from oracle import oracle as O
+    te = O.Tube(**dict(params, nx=16, z_min=-0.5, z_max=0.5))
+    return O.fields(te, O.init(te, state, state))[:, 0]
+
+
+def _whole_tube_checks(lat, params, nsteps, tot0, tol, tot_tol):
+    """Checks over every cell of a full-size tube: cells farther than
+    9 nsteps from the split (three stages of three-cell stencils per step)
+    still hold the fields of their side's initial state, and the totals obey
+    the conservation laws (N0, T00 constant; T0z grows by (P_L - P_R) t)."""
+    import torch
+    nx = params["nx"]
+    f = lat.fields(0)
+    c, pad = nx // 2, 9 * nsteps
+    sides = [_side_fields(params, SOD_L), _side_fields(params, SOD_R)]
+    # per-field scale: the larger side value; N^z, T^{0z} and v vanish at rest
+    # and are measured against N^0, T^{00} and 1
+    scale = np.maximum(np.abs(sides[0]), np.abs(sides[1]))
+    scale[1], scale[3], scale[7] = scale[0], scale[2], 1.0
+    scale_t = torch.tensor(scale, dtype=torch.float64, device=f.device)
+    worst = 0.0
+    for region, side_np in ((slice(0, c - pad), sides[0]), (slice(c + pad, nx), sides[1])):
+        side = torch.tensor(side_np, dtype=torch.float64, device=f.device)
+        dev = (f[:, region] - side[:, None]).abs().amax(dim=1) / scale_t
+        worst = max(worst, float(dev.max()))
+    tot = lat.totals(0)
+    t = lat.info(0)["time"]
+    drift = np.abs(tot - tot0 - np.array([0.0, 0.0, (SOD_L[0] - SOD_R[0]) * t])) / tot0[1]
+    print(f"[whole tube nx={nx}] outer cells max rel dev {worst:.2e}, totals drift {drift}", flush=True)
+    assert worst < tol
+    assert drift.max() < tot_tol
+
+
+def _window_check(params, precision, nsteps, half=256, tol=1e-12, outer_tol=None, tot_tol=None):
+    """Full-size run on the GPU; the oracle follows a window around z = 0, and
+    every cell outside the disturbed region is checked against its side's
+    initial state."""
     from oracle import oracle as O
     nx = params["nx"]
     lat = _lattice([params], precision=precision)
     dt = lat.info(0)["dt"]
     lat.set_initial_state(SOD_L, SOD_R)
+    tot0 = lat.totals(0)
     lat.step(nsteps)
     full = lat.moments(0)
+    _whole_tube_checks(lat, params, nsteps, tot0, outer_tol if outer_tol else (1e-13 if precision == "fp64" else 1e-6),
+                       tot_tol if tot_tol else (1e-13 if precision == "fp64" else 1e-6))
     F_gpu = lat.state_array(0) if nx * params["q_xi"] * params["q_p"] <= (1 << 28) else None
     c = nx // 2
     pad = 9 * nsteps
@@ -293,7 +333,10 @@ def test_maximum_tube_length(torch_cuda, precision, tol):
     params = dict(nx=nx, q_xi=4, q_p=3, tau=1e-2)
     lat = _lattice([params], precision=precision)
     lat.set_initial_state(SOD_L, SOD_R)
+    tot0 = lat.totals(0)
     lat.step(nsteps)
+    _whole_tube_checks(lat, params, nsteps, tot0, 1e-13 if precision == "fp64" else 1e-6,
+                       1e-13 if precision == "fp64" else 1e-6)
     f = lat.fields(0)
     c, pad = nx // 2, 9 * nsteps
     centre = f[:, c - half: c + half].cpu().numpy()
@@ -414,8 +457,10 @@ def test_autotuner_restores_state_and_keeps_results(torch_cuda, tmp_path):
     lat = _lattice(plist)
     lat.set_initial_states(w["left"], w["right"])
     lat.step(3)
+    clocks = [lat.info(k)["time"] for k in range(len(plist))]
     best, timings = autotune.tune(lat, steps=2, cache_path=str(tmp_path / "cache.json"))
     assert best in [dict(c) for c in autotune.CANDIDATES] and len(timings) == len(autotune.CANDIDATES)
+    assert [lat.info(k)["time"] for k in range(len(plist))] == clocks  # the sweep's steps do not count
     lat.step(3)
     for k in (0, 17, 39):
         assert np.array_equal(lat.state_array(k), ref.state_array(k))
