@@ -312,7 +312,13 @@ const char* rlb_last_error(const rlb_lattice* lat);
  *   q_xi, q_phi, q_p, n_v, n_p -- as for a tube (n_v <= 7), plus
  *                 n_v + 3 <= q_phi <= 64 (the azimuthal rule integrates the
  *                 moments of the equilibrium exactly);
- *   tau, T0, weno_eps -- as for a tube;
+ *   tau, T0    -- as for a tube;
+ *   weno_eps   -- as for a tube, in [1e-10, 1e8] for FP32 planes and
+ *                 [1e-70, 1e70] for FP64 (the plane's weights are always
+ *                 taken in product form, which needs this range; in FP32 the
+ *                 weight-free F should also stay below ~1e3 in magnitude,
+ *                 beyond which the products overflow and the cell is flagged
+ *                 non-physical);
  *   dt         -- > 0: explicit; 0: min(cfl / (1/dx + 1/dz), dt_tau_max tau).
  *                 dt (1/dx + 1/dz) <= 1.5 and dt <= 2.5 tau are required.
  *

@@ -232,10 +232,12 @@ __device__ inline void feq_coefficients(Real n, Real T, Real gamma, Real u, Real
 //   w0 = e1^2 e2^2, w1 = e0^2 e2^2, w2 = e0^2 e1^2,  e_r = 4 (eps + beta_r).
 // The products are fourth powers of the e_r: when the denominator comes out
 // zero, subnormal, infinite or NaN (in FP32: e_r below ~1e-10 on smooth data,
-// e.g. eps <= 1e-12, or above ~1e9, e.g. eps >= 1e9 or huge jumps) the lanes
-// concerned take the weights in the form w_r = (min_s e_s / e_r)^2 instead,
+// e.g. eps <= 1e-12, or above ~1e9, e.g. eps >= 1e9 or huge jumps) the face
+// is evaluated again with the weights in the form w_r = (min_s e_s / e_r)^2,
 // which lie in (0, 1] with at least one equal to 1 and cannot under- or
-// overflow (three exact divisions, off the common path).
+// overflow (three exact divisions; weno5_scaled).  weno5 reports through `ok`
+// whether its denominator was usable; callers that batch many faces recompute
+// only the rare bad ones.
 __device__ inline float weno_recip(float num, float den) { return num * __builtin_amdgcn_rcpf(den); }
 __device__ inline double weno_recip(double num, double den) {
   double r = __builtin_amdgcn_rcp(den);
@@ -248,27 +250,66 @@ __device__ inline bool weno_den_ok(Real den) {
   return __builtin_isfpclass(den, 0x100);
 }
 
+// Every multiply-add below is written as an explicit fused multiply-add (and
+// contraction is off), so that each inlined copy of a face -- a lane's own
+// face, the tile's extra face, the plane's x and z faces -- rounds the same
+// way and results do not depend on the tiling.
 template <typename Real>
-__device__ inline Real weno5(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps4) {
+struct WenoTerms {
+  Real e0, e1, e2, R0, R1, R2;
+};
+
+template <typename Real>
+__device__ inline WenoTerms<Real> weno5_terms(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps4) {
+#pragma clang fp contract(off)
   const Real a = v2 - v1, b = v3 - v2, c = v4 - v3, d = v5 - v4;
   const Real t0 = b - a, t1 = c - b, t2 = d - c;
-  const Real s0 = Real(3) * b - a, s1 = b + c, s2 = d - Real(3) * c;
+  const Real s0 = fma(b, Real(3), -a), s1 = b + c, s2 = fma(c, Real(-3), d);
   const Real k = Real(13.0 / 3.0);
-  const Real e0 = (k * t0) * t0 + (s0 * s0 + eps4);
-  const Real e1 = (k * t1) * t1 + (s1 * s1 + eps4);
-  const Real e2 = (k * t2) * t2 + (s2 * s2 + eps4);
-  const Real A = e0 * e0, B = e1 * e1, C = e2 * e2;
-  const Real w0 = B * C, w1 = A * C, w2 = A * B;
-  const Real R0 = Real(0.5) * b + Real(1.0 / 3.0) * t0;  // P0 / 6
-  const Real R1 = b + Real(2) * c;                         // P1
-  const Real R2 = Real(1.5) * c - Real(0.5) * t2;         // P2 / 2
-  const Real num = w0 * R0 + w1 * R1 + w2 * R2;
-  const Real den = w0 + Real(6) * w1 + Real(3) * w2;
-  if (__builtin_expect(weno_den_ok(den), 1)) return v3 + weno_recip(num, den);
-  const Real m = fmin(e0, fmin(e1, e2));
-  const Real q0 = m / e0, q1 = m / e1, q2 = m / e2;
+  WenoTerms<Real> w;
+  w.e0 = fma(t0, k * t0, fma(s0, s0, eps4));
+  w.e1 = fma(t1, k * t1, fma(s1, s1, eps4));
+  w.e2 = fma(t2, k * t2, fma(s2, s2, eps4));
+  w.R0 = fma(Real(0.5), b, Real(1.0 / 3.0) * t0);  // P0 / 6
+  w.R1 = fma(Real(2), c, b);                        // P1
+  w.R2 = fma(c, Real(1.5), -(Real(0.5) * t2));      // P2 / 2
+  return w;
+}
+
+// The same face value with the scaled weights (any positive eps, any data).
+template <typename Real>
+__device__ inline Real weno5_scaled(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps4) {
+#pragma clang fp contract(off)
+  const WenoTerms<Real> w = weno5_terms(v1, v2, v3, v4, v5, eps4);
+  const Real m = fmin(w.e0, fmin(w.e1, w.e2));
+  const Real q0 = m / w.e0, q1 = m / w.e1, q2 = m / w.e2;
   const Real x0 = q0 * q0, x1 = q1 * q1, x2 = q2 * q2;
-  return v3 + (x0 * R0 + x1 * R1 + x2 * R2) / (x0 + Real(6) * x1 + Real(3) * x2);
+  const Real num = fma(w.R2, x2, fma(w.R0, x0, w.R1 * x1));
+  const Real den = fma(Real(3), x2, fma(x1, Real(6), x0));
+  return v3 + num / den;
+}
+
+// Product form; ok is cleared when its denominator is not a positive normal
+// number (the value returned is then to be replaced by weno5_scaled).
+template <typename Real>
+__device__ inline Real weno5(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps4, bool& ok) {
+#pragma clang fp contract(off)
+  const WenoTerms<Real> w = weno5_terms(v1, v2, v3, v4, v5, eps4);
+  const Real A = w.e0 * w.e0, B = w.e1 * w.e1, C = w.e2 * w.e2;
+  const Real w0 = B * C, w1 = A * C, w2 = A * B;
+  const Real num = fma(w.R2, w2, fma(w.R0, w0, w.R1 * w1));
+  const Real den = fma(Real(3), w2, fma(w1, Real(6), w0));
+  ok = ok && weno_den_ok(den);
+  return v3 + weno_recip(num, den);
+}
+
+// One face, falling back to the scaled weights in place.
+template <typename Real>
+__device__ inline Real weno5(Real v1, Real v2, Real v3, Real v4, Real v5, Real eps4) {
+  bool ok = true;
+  const Real h = weno5(v1, v2, v3, v4, v5, eps4, ok);
+  if (__builtin_expect(ok, 1)) return h;
+  return weno5_scaled(v1, v2, v3, v4, v5, eps4);
 }
 
 // ---------------------------------------------------------------------------

@@ -46,10 +46,18 @@ constexpr int high_aux_pairs(int nv) { return 4 * ((nv + kHighExactMargin + 15) 
 // rows of Ze, Zo: ceil(q_xi / 2) rounded up to the MFMA's M = 16 (zero rows)
 constexpr int high_rows(int qx) { return 16 * (((qx + 1) / 2 + 15) / 16); }
 
-// Range of the WENO5 epsilon: 4 eps must be a positive number of the lattice's
-// precision with room to spare, and e_r = 4 (eps + beta_r) finite.
+// Range of the WENO5 epsilon.  Tubes: 4 eps must be a positive number of the
+// lattice's precision with room to spare, and e_r = 4 (eps + beta_r) finite
+// (the stage kernel switches to scaled weights where the product form of the
+// weights under- or overflows).  Planes use the product form only, which
+// needs (4 eps)^4 above the smallest normal number and e_r^4 below the
+// largest: eps in [1e-10, 1e8] in FP32 (for |F| up to ~1e3), [1e-70, 1e70]
+// in FP64.
 inline bool weno_eps_in_range(double eps, bool fp32) {
   return eps >= (fp32 ? 1e-40 : 1e-300) && eps <= 1e30;
+}
+inline bool plane_weno_eps_in_range(double eps, bool fp32) {
+  return fp32 ? (eps >= 1e-10 && eps <= 1e8) : (eps >= 1e-70 && eps <= 1e70);
 }
 
 // Sticky device flags.

@@ -100,9 +100,14 @@ struct LdsVec {
 // WENO value at the face between tile positions k+2 and k+3 (left face of the
 // cell stored at k+3) from the six values r[k..k+5], upwinded by the sign of xi.
 template <typename Real>
-__device__ inline Real face_value(const Real r[6], bool positive, Real eps) {
-  if (positive) return weno5(r[0], r[1], r[2], r[3], r[4], eps);
-  return weno5(r[5], r[4], r[3], r[2], r[1], eps);
+__device__ inline Real face_value(const Real r[6], bool positive, Real eps, bool& ok) {
+  if (positive) return weno5(r[0], r[1], r[2], r[3], r[4], eps, ok);
+  return weno5(r[5], r[4], r[3], r[2], r[1], eps, ok);
+}
+template <typename Real>
+__device__ inline Real face_value_scaled(const Real r[6], bool positive, Real eps) {
+  if (positive) return weno5_scaled(r[0], r[1], r[2], r[3], r[4], eps);
+  return weno5_scaled(r[5], r[4], r[3], r[2], r[1], eps);
 }
 
 __device__ inline void raise_flag(unsigned* flag, unsigned bits) { atomicOr(flag, bits); }
@@ -300,6 +305,7 @@ void stage_kernel(StageArgs<Real> a) {
 #pragma unroll
       for (int c = 0; c < CH; ++c) pos_mask |= uint32_t(jtab[min(j0 + c, qx - 1) * kJStride] >= Real(0)) << c;
       Real own[CH];
+      bool ok = true;  // every face of this lane had a usable product-form denominator
 #pragma unroll
       for (int h = 0; h < NH; ++h) {
         Vec rv[6];
@@ -313,7 +319,7 @@ void stage_kernel(StageArgs<Real> a) {
 #pragma unroll
             for (int k = 0; k < 6; ++k) r[k] = rv[k][e];
             const bool pos = decltype(dir)::value == 1 ? true : decltype(dir)::value == 0 ? false : ((hm >> e) & 1u);
-            own[h * V + e] = face_value(r, pos, eps4);
+            own[h * V + e] = face_value(r, pos, eps4, ok);
             __builtin_amdgcn_sched_barrier(0);  // one face at a time
           }
         };
@@ -336,7 +342,19 @@ void stage_kernel(StageArgs<Real> a) {
         Real r[6];
 #pragma unroll
         for (int k = 0; k < 6; ++k) r[k] = tile[t / V][TILE + k][t % V];
-        faces[t / V][TILE][t % V] = face_value(r, (pos_mask >> t) & 1u, eps4);
+        bool ok_last = true;
+        const Real h = face_value(r, (pos_mask >> t) & 1u, eps4, ok_last);
+        faces[t / V][TILE][t % V] = ok_last ? h : face_value_scaled(r, (pos_mask >> t) & 1u, eps4);
+      }
+      if (__builtin_expect(!ok, 0)) {
+        // rare: a face's product-form weights under- or overflowed; this
+        // lane's faces of the chunk again with the scaled weights
+#pragma unroll 1
+        for (int c = 0; c < CH; ++c) {
+          Real r[6];
+          for (int k = 0; k < 6; ++k) r[k] = tile[c / V][t + k][c % V];
+          faces[c / V][t][c % V] = face_value_scaled(r, (pos_mask >> c) & 1u, eps4);
+        }
       }
       __syncthreads();
       const int cj = min(CH, qx - j0);

@@ -189,13 +189,18 @@ using BufTag = std::integral_constant<int, B>;
 // 5 .. 1 otherwise).  `up` is wave-uniform; the empty asm statement keeps the
 // two orientations as separate branches, each reading LDS at immediate
 // offsets, instead of one merged body that computes its LDS addresses.
+// The product form of the weights only: the plane's epsilon is validated to
+// the range in which it neither under- nor overflows for |F| up to ~1e3
+// (FP32; see weno_eps_in_range).
 template <typename Real, int ST>
 __device__ inline Real face(const Real* p, bool up, Real eps4) {
-  if (up) return weno5(p[0], p[ST], p[2 * ST], p[3 * ST], p[4 * ST], eps4);
-  Real h = weno5(p[5 * ST], p[4 * ST], p[3 * ST], p[2 * ST], p[ST], eps4);
+  bool unused = true;
+  if (up) return weno5(p[0], p[ST], p[2 * ST], p[3 * ST], p[4 * ST], eps4, unused);
+  Real h = weno5(p[5 * ST], p[4 * ST], p[3 * ST], p[2 * ST], p[ST], eps4, unused);
   asm volatile("" : "+v"(h));
   return h;
 }
+
 
 // Occupancy: 6 waves per SIMD (three workgroups) for FP32 and 4 for FP64
 // with Q_p <= 4, 4 for FP32 in the generic Q_p <= 8 group (the per-cell

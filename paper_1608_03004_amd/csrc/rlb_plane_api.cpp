@@ -198,8 +198,8 @@ rlb_status rlb_plane_create(const rlb_plane_desc* desc, rlb_precision prec, rlb_
   std::string msg;
   const rlb_status st = validate_plane(*desc, msg);
   if (st != RLB_OK) return pfail(nullptr, st, msg);
-  if (!rlb::weno_eps_in_range(desc->weno_eps, prec == RLB_FP32))
-    return pfail(nullptr, RLB_ERR_INVALID_ARG, "weno_eps must lie in [1e-40, 1e30] (FP32) or [1e-300, 1e30] (FP64)");
+  if (!rlb::plane_weno_eps_in_range(desc->weno_eps, prec == RLB_FP32))
+    return pfail(nullptr, RLB_ERR_INVALID_ARG, "weno_eps must lie in [1e-10, 1e8] (FP32) or [1e-70, 1e70] (FP64)");
   const rlb_plane_desc& d = *desc;
   std::vector<double> xi, wxi, p, wp;
   if (!gauss_legendre_rule(d.q_xi, xi, wxi) || !gauss_laguerre1_rule(d.q_p, p, wp))

@@ -119,9 +119,19 @@ def test_weno_epsilon_outside_its_range_is_rejected(lib, eps, prec):
     st, h = _create(lib, [rlb.Tube(nx=64, weno_eps=eps)], prec=prec)
     assert st == rlb.RLB_ERR_INVALID_ARG and not h.value
     assert b"weno_eps" in lib.rlb_last_error(None)
+
+
+@pytest.mark.parametrize("eps,prec,ok", [(1e-11, rlb.RLB_FP32, False), (1e-10, rlb.RLB_FP32, True),
+                                         (1e8, rlb.RLB_FP32, True), (1e9, rlb.RLB_FP32, False),
+                                         (1e-71, rlb.RLB_FP64, False), (1e70, rlb.RLB_FP64, True),
+                                         (math.inf, rlb.RLB_FP64, False)])
+def test_plane_weno_epsilon_range(lib, eps, prec, ok):
     pd = rlb.PlaneSpec(weno_eps=eps).c()
     ph = ctypes.c_void_p()
-    assert lib.rlb_plane_create(ctypes.byref(pd), prec, ctypes.byref(ph)) == rlb.RLB_ERR_INVALID_ARG
+    st = lib.rlb_plane_create(ctypes.byref(pd), prec, ctypes.byref(ph))
+    assert (st == 0) == ok
+    if ph.value:
+        lib.rlb_plane_destroy(ph)
 
 
 def test_high_order_tubes_create_without_adjoint(lib):
