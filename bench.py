@@ -6,23 +6,34 @@ left/right states) -- advanced by full SSP-RK3 steps in the FP32 form (FP32
 stencil and relaxation, Kahan-compensated FP32 moment sums, FP64 Landau
 matching).  A "step" is one full time step (three stage launches) of the
 whole tube.  Beside it, on the same line:
-  fp64        the FP64 form on the same tube, and the FP32-vs-FP64 error table
-              (max and L2 relative errors of e, v, T^{mu nu}) after the run;
+  fp64        the FP64 form on the same tube;
+  tau_sweep   the large tube for its 2000 steps at tau = 1e-4, 1e-2, 1, 100 in
+              FP32 and FP64: throughput, FP32-vs-FP64 max/L2 errors of e, u,
+              T^{mu nu} over the whole tube, and at tau = 100 the error
+              against the free-streaming profile of eq. ballistic;
   batched     4096 seeded tubes of uneven size, order and tau in one launch
               per stage, schedule chosen by the autotuner, replayed from a
               hipGraph;
   adjoint     gradient of the profile loss of the 4096-cell, Q = 32 x 3 tube
-              over 2000 steps (forward + sqrt(N)-checkpointed backward);
-  ballistic   the 2^22-cell, Q = 256 x 4 tube at tau = 1e3 (FP32);
+              over 2000 steps (forward + sqrt(N)-checkpointed backward), with
+              central differences (h = 1e-6) at full size;
+  ballistic   the 2^22-cell, Q = 256 x 4 tube at tau = 1e3 (FP32): a short
+              timed run, and the full 4000-step run against eq. ballistic;
   high        the headline tube with the high-order equilibrium (N_v = 63),
               FP32 and FP64, with the matrix-core roofline of its pre-pass;
   plane       the multi-dimensional model on a 1024 x 1024 plane (Q = 120),
               FP32 and FP64;
+  copy, stream the practical HBM ceilings: a plain copy, and the stage
+              kernel's own memory pattern with no arithmetic;
   roofline    of the stage kernel: algorithmic bytes per launch over its mean
               duration, timed with HIP events on the launch stream;
-  cpu_baseline the CPU FP64 oracle on a bounded sample of the headline tube.
+  cpu_baseline the CPU FP64 oracle on a bounded sample of the headline tube,
+              and on the windows of every leg's result that it can follow
+              (the max and L2 errors of e, u and T^{mu nu} against the FP64
+              oracle are attached to each leg as oracle_error).
 
-Prints ONE JSON line.  Inputs are resident in HBM before every timed region.
+Prints ONE JSON line (progress lines go to stderr).  Inputs are resident in
+HBM before every timed region.
 """
 import argparse
 import json
@@ -66,6 +77,10 @@ TRAFFIC_FILES = {"stage_kernel": "stage_kernel_traffic.json", "feq_kernel": "feq
                  "plane_stage_kernel": "plane_stage_kernel_traffic.json"}
 
 
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def kernel_source_sha1(kernel="stage_kernel"):
     """SHA-1 of the sources a kernel is built from (its own file and the two
     shared headers)."""
@@ -77,20 +92,21 @@ def kernel_source_sha1(kernel="stage_kernel"):
     return h.hexdigest()
 
 
-def measured_traffic(precision, kernel="stage_kernel"):
-    """HBM bytes per launch of a kernel on its benchmark workload from the
-    committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs (calibrated on the copy
-    kernel), or None when the kernel's sources changed since those counters
-    were taken."""
+def measured_traffic(workload, kernel="stage_kernel"):
+    """HBM bytes per launch of a kernel on a benchmark workload (e.g.
+    "sod_large/fp32") from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE runs
+    (calibrated on the copy kernel), or None when the kernel's sources changed
+    since those counters were taken."""
     path = os.path.join(ROOT, "profiles", TRAFFIC_FILES[kernel])
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_source_sha1") != kernel_source_sha1(kernel) or precision not in t:
+    if t.get("kernel_source_sha1") != kernel_source_sha1(kernel):
         return None
-    return int(t[precision]["traffic_bytes_per_launch"])
+    w = t.get("workloads", {}).get(workload)
+    return int(w["traffic_bytes_per_launch"]) if w else None
 
 
 def roofline(tubes, rsize, steps, event_s, traffic=None):
@@ -102,7 +118,71 @@ def roofline(tubes, rsize, steps, event_s, traffic=None):
                 bytes_per_launch=int(bytes_launch), launch_us=round(launch_s * 1e6, 2))
 
 
-def leg_single(precision, params, steps, warmup, schedule=None):
+# ---------------------------------------------------------------------------
+# Reference profiles the benchmark checks against (closed forms of the paper)
+# ---------------------------------------------------------------------------
+DN = SOD_L[1] - SOD_R[1]  # the normalisation of the paper's error measure
+
+
+def n_ballistic(z, t, nL=1.0, nR=0.125):
+    """Density of free streaming from the Sod states (eq. ballistic): with
+    s = z/t, |N| = sqrt(((nL+nR)/2 - (nL-nR) s/2)^2 - ((nL-nR)/4)^2 (1-s^2)^2)."""
+    import numpy as np
+    s = np.clip(np.asarray(z, dtype=np.float64) / t, -1.0, 1.0)
+    return np.sqrt(((nL + nR) / 2 - (nL - nR) / 2 * s) ** 2 - ((nL - nR) / 4) ** 2 * (1 - s * s) ** 2)
+
+
+def staircase_bound(xi, w, nL=1.0, nR=0.125):
+    """Largest deviation (in units of nL - nR) of the discrete-velocity free
+    streaming, every polar node xi_j moving exactly, from eq. ballistic: the
+    error of the quadrature itself, which the lattice run approaches."""
+    import numpy as np
+    s = np.linspace(-0.999999, 0.999999, 200001)[None, :]
+    left = (s < np.asarray(xi)[:, None])  # node j at z = s t came from the left iff xi_j > s
+    n = np.where(left, nL, nR)
+    wj = np.asarray(w)[:, None] / 2
+    N0, Nz = (wj * n).sum(0), (wj * n * np.asarray(xi)[:, None]).sum(0)
+    return float(np.abs(np.sqrt(N0 * N0 - Nz * Nz) - n_ballistic(s[0], 1.0, nL, nR)).max() / (nL - nR))
+
+
+FIELD_ROWS = dict(e=5, T00=2, T0z=3, Tzz=4, N0=0, n=6)
+
+
+def error_table(a, b):
+    """Max and L2 relative errors (normwise per field) of fields a against b:
+    e, u = gamma v, T^{mu nu}, N^0 and n."""
+    import numpy as np
+    out = {}
+    for name, k in FIELD_ROWS.items():
+        d = a[k] - b[k]
+        s = max(np.abs(b[k]).max(), 1e-300)
+        out[name] = dict(max=float(np.abs(d).max() / s), l2=float(np.sqrt(np.mean(d * d)) / s))
+    ua, ub = a[7] / np.sqrt(1 - a[7] ** 2), b[7] / np.sqrt(1 - b[7] ** 2)
+    s = max(np.abs(ub).max(), 1e-300)
+    out["u"] = dict(max=float(np.abs(ua - ub).max() / s), l2=float(np.sqrt(np.mean((ua - ub) ** 2)) / s))
+    return out
+
+
+def window_request(name, params, left, right, nsteps, dt, fields, half=256):
+    """A centre window of a full-tube result that the oracle can follow: the
+    initial state of cells [c - half - 9 n, c + half + 9 n) evolves exactly
+    like the full tube on its inner 2 half cells (three stages of three-cell
+    stencils per step); whole tubes when they are short."""
+    nx = params["nx"]
+    pad = 9 * nsteps
+    c = nx // 2
+    a, b = max(0, c - half - pad), min(nx, c + half + pad)
+    lo, hi = (0, nx) if (a == 0 or b == nx) else (c - half, c + half)
+    if lo == 0 and hi == nx:
+        a, b = 0, nx
+    return dict(name=name, params=dict(params), left=left, right=right, nsteps=nsteps, dt=dt, a=a, b=b, lo=lo,
+                hi=hi, gpu=fields[:, lo:hi].copy())
+
+
+# ---------------------------------------------------------------------------
+# Legs
+# ---------------------------------------------------------------------------
+def leg_single(precision, params, steps, warmup, schedule=None, traffic_key=None):
     from paper_1608_03004_amd import Lattice, Tube
     tube = Tube(**params)
     lat = Lattice([tube], precision=precision)
@@ -114,25 +194,64 @@ def leg_single(precision, params, steps, warmup, schedule=None):
     wall, ev = timed_steps(lat, steps)
     fields = lat.moments(0)
     rsize = 4 if precision == "fp32" else 8
-    traffic = measured_traffic(precision) if (tube.nx, tube.q_xi, tube.q_p) == (1 << 20, 64, 4) else None
+    traffic = measured_traffic(traffic_key) if traffic_key else None
     out = dict(value=tube.nx * tube.Q * steps / wall, ms_per_step=1e3 * wall / steps,
                roofline=roofline([tube], rsize, steps, ev, traffic), schedule=lat.get_schedule())
-    return out, fields, lat
+    win = window_request(f"sod_large/{precision}", params, SOD_L, SOD_R, steps + warmup, lat.info(0)["dt"], fields)
+    return out, fields, lat, win
 
 
-def error_table(f32, f64):
-    """Max and L2 relative errors (normwise per field) of FP32 against FP64."""
+def leg_tau_sweep(nsteps=2000, taus=(1e-4, 1e-2, 1.0, 100.0)):
+    """The large tube for its stated 2000 steps at each tau, FP32 and FP64."""
     import numpy as np
-    names = dict(e=5, v=7, T00=2, T0z=3, Tzz=4, N0=0, n=6)
-    out = {}
-    for name, k in names.items():
-        d = f32[k] - f64[k]
-        s = max(np.abs(f64[k]).max(), 1e-300)
-        out[name] = dict(max=float(np.abs(d).max() / s), l2=float(np.sqrt(np.mean(d * d)) / s))
-    return out
+    import torch
+    from paper_1608_03004_amd import Lattice, Tube
+    res = {}
+    for tau in taus:
+        r, f = {}, {}
+        for prec in ("fp32", "fp64"):
+            tube = Tube(nx=1 << 20, q_xi=64, q_p=4, tau=tau)
+            lat = Lattice([tube], precision=prec)
+            lat.set_initial_state(SOD_L, SOD_R)
+            tot0 = lat.totals(0)
+            wall, ev = timed_steps(lat, nsteps)
+            f[prec] = lat.moments(0)
+            tot = lat.totals(0)
+            t = lat.info(0)["time"]
+            flags = lat.flags()
+            rsize = 4 if prec == "fp32" else 8
+            # conservation (A19): N0, T00 constant; T0z grows by (P_L - P_R) t
+            drift = (tot - tot0 - np.array([0.0, 0.0, (SOD_L[0] - SOD_R[0]) * t])) / tot0[1]
+            r[prec] = dict(value=tube.nx * tube.Q * nsteps / wall, ms_per_step=1e3 * wall / nsteps,
+                           roofline=roofline([tube], rsize, nsteps, ev), conservation_drift=drift.tolist(),
+                           fast_flow=flags["fast_flow"])
+            if tau == 100.0:
+                xi, w, _, _ = lat.tables(0)
+                z = -0.5 + (np.arange(tube.nx) + 0.5) / tube.nx
+                r[prec]["ballistic_error"] = float(np.abs(f[prec][9] - n_ballistic(z, t)).max() / DN)
+                r["staircase_bound"] = staircase_bound(xi, w)
+            del lat
+            torch.cuda.empty_cache()
+        r["fp32_vs_fp64_error"] = error_table(f["fp32"], f["fp64"])
+        r["speedup_fp32_over_fp64"] = r["fp32"]["value"] / r["fp64"]["value"]
+        r["t_end"] = t
+        res[f"tau={tau:g}"] = r
+        progress(f"tau sweep: tau = {tau:g} done")
+    res["workload"] = "sod_large: N_x=2^20, Q=64x4, 2000 steps, tau in {1e-4, 1e-2, 1, 100}, FP32 and FP64"
+    return res
 
 
-def leg_batched(steps, tune=True):
+def batched_selection(w):
+    """Tubes of the seeded draw whose results are checked against the oracle:
+    the first of every polar order, the stiffest and the shortest."""
+    import numpy as np
+    tubes = w["tubes"]
+    sel = [next(k for k, t in enumerate(tubes) if t["q_xi"] == q) for q in (8, 16, 32, 64, 128)]
+    sel += [int(np.argmin([t["tau"] for t in tubes])), int(np.argmin([t["nx"] for t in tubes]))]
+    return sorted(set(sel))
+
+
+def leg_batched(steps, schedule=None):
     import torch
     import workloads
     from paper_1608_03004_amd import Lattice, Tube
@@ -142,27 +261,36 @@ def leg_batched(steps, tune=True):
     lat = Lattice(tubes, precision="fp32")
     lat.set_initial_states(w["left"], w["right"])
     lat.step(1)
-    sched, timings = (autotune.tune(lat, steps=3, use_cache=False) if tune else (None, {}))
+    if schedule:  # a fixed schedule (profiling runs), no autotuning
+        lat.set_schedule(**schedule)
+        timings = {}
+    else:
+        _, timings = autotune.tune(lat, steps=3, use_cache=False)
     lat.set_initial_states(w["left"], w["right"])
-    lat.step(2)
+    warm = 2
+    lat.step(warm)
     lat.check()
     wall, ev = timed_steps(lat, steps)
     lat.check()
     pts = sum(t.nx * t.Q for t in tubes)
-    best = sorted(timings.values())[:1]
+    wins = []
+    for k in batched_selection(w):
+        wins.append(window_request(f"sod_batched/tube{k}", w["tubes"][k], w["left"][k], w["right"][k],
+                                   warm + steps, lat.info(k)["dt"], lat.moments(k)))
     out = dict(value=pts * steps / wall, unit="cell*quad-point updates/s", ms_per_step=1e3 * wall / steps,
                steps=steps, tubes=len(tubes), points_per_step=pts, schedule=lat.get_schedule(),
-               roofline=roofline(tubes, 4, steps, ev),
+               roofline=roofline(tubes, 4, steps, ev, measured_traffic("sod_batched/fp32")),
                autotune_candidates=len(timings),
                workload="sod_batched: 4096 tubes, numpy default_rng(0): N_x~U{256..8192}, "
                         "Q_xi~U{8,16,32,64,128}, Q_p=3, log tau~U[ln1e-4,ln10], "
                         "log(P_L/P_R)~U[ln2,ln100], n_L/n_R~U[1,10], FP32")
     del lat
     torch.cuda.empty_cache()
-    return out
+    return out, wins
 
 
-def leg_adjoint(precision, nsteps=2000):
+def leg_adjoint(precision, nsteps=2000, fd=False):
+    import numpy as np
     import torch
     import workloads
     from paper_1608_03004_amd import Lattice, Tube
@@ -200,27 +328,63 @@ def leg_adjoint(precision, nsteps=2000):
                grad_tau=grads[0], grad_P_L=grads[1], grad_n_L=grads[2], loss=float(loss.detach()),
                workload="sod_adjoint: N_x=4096, Q=32x3, 2000 steps, dt=0.5 dz, start (tau,P_L,n_L)=(0.02,1,1), "
                         "target from (0.05,1.5,1)")
+    if fd:
+        # central differences of the forward at h = 1e-6 (FP64), dt fixed
+        tgt = target.cpu().numpy()
+
+        def loss_at(tau, PL):
+            plat = Lattice([Tube(**p)], precision="fp64")
+            plat.set_tau(tau)
+            plat.set_initial_state((PL, st["n_L"], 0.0), SOD_R)
+            plat.step(nsteps)
+            return float(np.sum((plat.moments(0)[5] - tgt) ** 2) / p["nx"])
+
+        h = 1e-6
+        fd_tau = (loss_at(st["tau"] + h, st["P_L"]) - loss_at(st["tau"] - h, st["P_L"])) / (2 * h)
+        fd_PL = (loss_at(st["tau"], st["P_L"] + h) - loss_at(st["tau"], st["P_L"] - h)) / (2 * h)
+        out["fd_h"] = h
+        out["fd_grad_tau"], out["fd_grad_P_L"] = fd_tau, fd_PL
+        out["fd_rel_err"] = dict(tau=abs(fd_tau - grads[0]) / abs(fd_tau), P_L=abs(fd_PL - grads[1]) / abs(fd_PL))
     del lat
     torch.cuda.empty_cache()
     return out
 
 
-def leg_ballistic(steps, warmup=2):
+def leg_ballistic(steps, warmup=2, full_steps=4000):
+    """The ballistic stress tube: a short timed run (throughput, and a window
+    the oracle can follow) and the stated 4000-step run against eq. ballistic."""
     import numpy as np
     import torch
     from paper_1608_03004_amd import Lattice, Tube
-    tube = Tube(nx=1 << 22, q_xi=256, q_p=4, tau=1e3)
+    params = dict(nx=1 << 22, q_xi=256, q_p=4, tau=1e3)
+    tube = Tube(**params)
     lat = Lattice([tube], precision="fp32")
     lat.set_initial_state(SOD_L, SOD_R)
     lat.step(warmup)
     wall, ev = timed_steps(lat, steps)
     lat.check()
+    win = window_request("sod_ballistic/fp32", params, SOD_L, SOD_R, steps + warmup, lat.info(0)["dt"],
+                         lat.moments(0))
     out = dict(value=tube.nx * tube.Q * steps / wall, ms_per_step=1e3 * wall / steps, steps=steps,
-               roofline=roofline([tube], 4, steps, ev),
+               roofline=roofline([tube], 4, steps, ev, measured_traffic("sod_ballistic/fp32")),
                workload="sod_ballistic: N_x=2^22, Q=256x4, tau=1e3, FP32")
+    progress("ballistic: short run done")
+    if full_steps:
+        lat.set_initial_state(SOD_L, SOD_R)
+        wall, ev = timed_steps(lat, full_steps)
+        f = lat.moments(0)
+        t = lat.info(0)["time"]
+        xi, w, _, _ = lat.tables(0)
+        z = -0.5 + (np.arange(tube.nx) + 0.5) / tube.nx
+        out["full_run"] = dict(steps=full_steps, t_end=t, value=tube.nx * tube.Q * full_steps / wall,
+                               ms_per_step=1e3 * wall / full_steps,
+                               roofline=roofline([tube], 4, full_steps, ev),
+                               ballistic_error=float(np.abs(f[9] - n_ballistic(z, t)).max() / DN),
+                               staircase_bound=staircase_bound(xi, w), flags=lat.flags())
+        progress("ballistic: 4000-step run done")
     del lat
     torch.cuda.empty_cache()
-    return out
+    return out, win
 
 
 MFMA_F64_PEAK_TFS = 78.6  # MI355X dense FP64 matrix
@@ -240,7 +404,8 @@ def leg_high_order(precision, steps, warmup=2, reps=10):
     streams its output."""
     import torch
     from paper_1608_03004_amd import Lattice, Tube
-    tube = Tube(nx=1 << 20, q_xi=64, q_p=4, n_v=63, tau=1e-2)
+    params = dict(nx=1 << 20, q_xi=64, q_p=4, n_v=63, tau=1e-2)
+    tube = Tube(**params)
     lat = Lattice([tube], precision=precision)
     lat.set_initial_state(SOD_L, SOD_R)
     lat.step(warmup)
@@ -248,6 +413,8 @@ def leg_high_order(precision, steps, warmup=2, reps=10):
     wall, ev = timed_steps(lat, steps)
     lat.check()
     fields = lat.moments(0)
+    win = window_request(f"sod_large_high_order/{precision}", params, SOD_L, SOD_R, steps + warmup,
+                         lat.info(0)["dt"], fields, half=64)
     # the pre-pass alone on the lattice's stream (same launch as inside a
     # stage), one launch per timing: inside a step each pre-pass alternates
     # with the memory-bound stage kernel, while back-to-back launches of the
@@ -273,7 +440,7 @@ def leg_high_order(precision, steps, warmup=2, reps=10):
                ms_per_step=1e3 * wall / steps, steps=steps,
                roofline=dict(bound="mfma", achieved=round(flops / feq_s / 1e12, 2), peak=MFMA_F64_PEAK_TFS,
                              unit="TFLOP/s", frac=round(flops / feq_s / 1e12 / MFMA_F64_PEAK_TFS, 4),
-                             traffic=measured_traffic(precision, "feq_kernel"),
+                             traffic=measured_traffic(f"sod_large_high_order/{precision}", "feq_kernel"),
                              kernel="feq_kernel", flops_per_launch=flops, launch_us=round(feq_s * 1e6, 2)),
                stage_roofline=dict(bound="hbm", achieved=round(stage_bytes / stage_s / 1e9, 1), peak=HBM_PEAK_GBS,
                                    unit="GB/s", frac=round(stage_bytes / stage_s / 1e9 / HBM_PEAK_GBS, 4),
@@ -281,7 +448,7 @@ def leg_high_order(precision, steps, warmup=2, reps=10):
                workload=f"sod_large_high_order: N_x=2^20, Q=64x4, N_v=63, N_p=2, tau=1e-2, {precision.upper()}")
     del lat, out
     torch.cuda.empty_cache()
-    return res, fields
+    return res, fields, win
 
 
 def plane_quadrants(nx, nz):
@@ -322,14 +489,16 @@ def plane_point_ops(spec):
     return 2 * 37 + (2 + spec.n_v) + 8 + 3 + 6
 
 
-def leg_plane(precision, steps, warmup=2):
+def leg_plane(precision, steps, warmup=2, window_steps=5, window_half=8):
     """The multi-dimensional model: a 1024 x 1024 plane, Q = 3 x 8 x 5 evolved
-    points (Q_phi = 8), a 2D Riemann problem."""
+    points (Q_phi = 8), a 2D Riemann problem; a separate short run gives a
+    centre window the oracle can follow."""
     import torch
     from paper_1608_03004_amd import Plane, PlaneSpec
     spec = PlaneSpec(nx=1024, nz=1024, q_xi=8, q_phi=8, q_p=3, tau=1e-2)
     gp = Plane(spec, precision=precision)
-    gp.set_initial_fields(plane_quadrants(spec.nx, spec.nz))
+    init = plane_quadrants(spec.nx, spec.nz)
+    gp.set_initial_fields(init)
     gp.step(warmup)
     gp.check()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -352,28 +521,40 @@ def leg_plane(precision, steps, warmup=2):
                steps=steps,
                roofline=dict(bound="hbm", achieved=round(bytes_launch / launch_s / 1e9, 1), peak=HBM_PEAK_GBS,
                              unit="GB/s", frac=round(bytes_launch / launch_s / 1e9 / HBM_PEAK_GBS, 4),
-                             traffic=measured_traffic(precision, "plane_stage_kernel"), kernel="plane_stage_kernel",
-                             bytes_per_launch=int(bytes_launch),
+                             traffic=measured_traffic(f"plane_quadrants/{precision}", "plane_stage_kernel"),
+                             kernel="plane_stage_kernel", bytes_per_launch=int(bytes_launch),
                              launch_us=round(launch_s * 1e6, 2)),
                roofline_alu=dict(bound="alu", achieved=round(ops_launch / launch_s / 1e9, 1), peak=VALU_PEAK_GOPS,
                                  unit="Gop/s", frac=round(ops_launch / launch_s / 1e9 / VALU_PEAK_GOPS, 4),
                                  kernel="plane_stage_kernel", ops_per_point=plane_point_ops(spec)),
                workload=f"plane_quadrants: 1024 x 1024 cells, Q = 3 x 8 x (8/2+1) = 120, N_v = 5, tau = 1e-2, "
                         f"2D Riemann problem, {precision.upper()}")
+    # the window: a short run from the same initial state
+    gp.set_initial_fields(init)
+    gp.step(window_steps)
+    short = gp.moments()
+    pad = 9 * window_steps
+    c = spec.nx // 2
+    a, b = c - window_half - pad, c + window_half + pad
+    win = dict(name=f"plane_quadrants/{precision}", plane=True,
+               spec=dict(nx=b - a, nz=b - a, q_xi=8, q_phi=8, q_p=3, tau=1e-2, x_min=-0.5 + a / spec.nx,
+                         x_max=-0.5 + b / spec.nx, z_min=-0.5 + a / spec.nz, z_max=-0.5 + b / spec.nz,
+                         dt=gp.info()["dt"]),
+               init=init[:, a:b, a:b].copy(), nsteps=window_steps, pad=pad, half=window_half,
+               gpu=short[:, c - window_half:c + window_half, c - window_half:c + window_half].copy())
     del gp
     torch.cuda.empty_cache()
-    return res, fields
+    return res, fields, win
 
 
-def plane_error_table(f32, f64):
-    """Max and L2 relative errors (normwise per field) of the FP32 plane
-    against the FP64 plane after the same steps."""
+def plane_error_table(a, b):
+    """Max and L2 relative errors (normwise per field) of plane fields."""
     import numpy as np
     names = dict(e=9, vx=11, vz=12, T00=3, T0x=4, T0z=5, Txx=6, Txz=7, Tzz=8, N0=0, n=10)
     out = {}
     for name, k in names.items():
-        d = f32[k] - f64[k]
-        s = max(np.abs(f64[k]).max(), 1e-300)
+        d = a[k] - b[k]
+        s = max(np.abs(b[k]).max(), 1e-300)
         out[name] = dict(max=float(np.abs(d).max() / s), l2=float(np.sqrt(np.mean(d * d)) / s))
     return out
 
@@ -403,10 +584,63 @@ def leg_copy(nbytes=1 << 30, reps=5):
                 verified=ok)
 
 
-def cpu_baseline(params, target_s=12.0):
-    """The CPU FP64 oracle on a bounded sample: the headline tube's Q and tau on
-    a sub-tube of 2^16 cells, timed over whole steps (12 to about 25 s of CPU
-    work)."""
+def leg_stream(rows=256, cols=1 << 20, reps=10):
+    """The stage kernel's memory pattern with no arithmetic (rlb_device_stream)
+    on the headline tube's array shape, FP32 and FP64: one read and one write
+    per point (stage 1), two reads and one write (stages 2, 3)."""
+    import torch
+    from paper_1608_03004_amd import rlb
+    res = {}
+    for prec, dtype in (("fp32", torch.float32), ("fp64", torch.float64)):
+        a = torch.rand(rows * cols, dtype=dtype, device="cuda")
+        b = torch.rand(rows * cols, dtype=dtype, device="cuda")
+        out = torch.empty_like(a)
+        r = {}
+        for name, bb, nacc in (("read1_write1", None, 2), ("read2_write1", b, 3)):
+            rlb.device_stream(out, a, bb, rows, cols, cols)
+            torch.cuda.synchronize()
+            start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            stream = torch.cuda.current_stream()
+            start.record(stream)
+            for _ in range(reps):
+                rlb.device_stream(out, a, bb, rows, cols, cols)
+            stop.record(stream)
+            torch.cuda.synchronize()
+            s = start.elapsed_time(stop) * 1e-3 / reps
+            byts = nacc * rows * cols * a.element_size()
+            ok = bool(torch.equal(out, a + b if bb is not None else a))
+            r[name] = dict(bytes=byts, us=round(s * 1e6, 2), achieved_GBs=round(byts / s / 1e9, 1),
+                           frac_of_peak=round(byts / s / 1e9 / HBM_PEAK_GBS, 4), verified=ok)
+        # a step moves one read1/write1 and two read2/write1 passes
+        step_s = (r["read1_write1"]["us"] + 2 * r["read2_write1"]["us"]) * 1e-6
+        r["step_us"] = round(step_s * 1e6, 2)
+        r["step_GBs"] = round(8 * rows * cols * a.element_size() / step_s / 1e9, 1)
+        res[prec] = r
+        del a, b, out
+        torch.cuda.empty_cache()
+    res["shape"] = f"[{rows}][{cols}] rows of the headline tube's state"
+    return res
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(params, windows, target_s=12.0):
+    """The CPU FP64 oracle: (1) on a bounded sample of the headline workload --
+    the headline tube's Q and tau on a sub-tube of 2^16 cells, timed over
+    whole steps (12 to about 25 s of CPU work); (2) on the windows of the GPU
+    results that it can follow, which gives every leg's max and L2 errors
+    against the oracle (its time is counted in the sample too)."""
+    import numpy as np
     from oracle import oracle as O
     nx = 1 << 16
     t = O.Tube(nx=nx, q_xi=params["q_xi"], q_p=params["q_p"], tau=params["tau"], dt=0.5 / params["nx"])
@@ -421,27 +655,60 @@ def cpu_baseline(params, target_s=12.0):
         secs += time.perf_counter() - t0
         n += k
         k = min(2 * k, 400 - n)
-    return dict(value=nx * t.Q * n / secs, unit="cell*quad-point updates/s", cores=O.num_threads(), kind="oracle",
+    sample_updates = nx * t.Q * n
+    errors, win_updates, win_secs = {}, 0, 0.0
+    for w in windows:
+        t0 = time.perf_counter()
+        if w.get("plane"):
+            pl = O.Plane(**w["spec"])
+            Fp = O.plane_run(pl, w["init"], w["nsteps"])
+            ref = O.plane_fields(pl, Fp)
+            p, h = w["pad"], w["half"]
+            ref = ref[:, p:p + 2 * h, p:p + 2 * h]
+            win_updates += pl.nx * pl.nz * pl.Q * w["nsteps"]
+            errors[w["name"]] = plane_error_table(w["gpu"], ref)
+        else:
+            nxf = w["params"]["nx"]
+            dz = 1.0 / nxf
+            wp = dict(w["params"], nx=w["b"] - w["a"], z_min=-0.5 + w["a"] * dz, z_max=-0.5 + w["b"] * dz, dt=w["dt"])
+            ot = O.Tube(**wp)
+            ref = O.fields(ot, O.run(ot, w["left"], w["right"], w["nsteps"]))
+            ref = ref[:, w["lo"] - w["a"]:w["hi"] - w["a"]]
+            win_updates += ot.nx * ot.Q * w["nsteps"]
+            errors[w["name"]] = error_table(w["gpu"], ref)
+            errors[w["name"]]["cells"] = [w["lo"], w["hi"]]
+            errors[w["name"]]["after_steps"] = w["nsteps"]
+        win_secs += time.perf_counter() - t0
+    base = dict(value=sample_updates / secs, unit="cell*quad-point updates/s", cores=O.num_threads(), kind="oracle",
+                cpu=cpu_model(), affinity_cpus=len(os.sched_getaffinity(0)),
                 sample=f"FP64 oracle on {nx} cells x Q={t.Q} ({params['q_xi']}x{params['q_p']}), tau={params['tau']}, "
-                       f"{n} steps in {secs:.1f} s (the headline tube's per-point work on 1/16 of its cells)")
+                       f"{n} steps in {secs:.1f} s (the headline tube's per-point work on 1/16 of its cells); plus "
+                       f"{len(windows)} windows of the legs' results ({win_updates:.3g} point updates in "
+                       f"{win_secs:.1f} s) for their oracle errors")
+    return base, errors
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--nx", type=int, default=1 << 20)
     ap.add_argument("--tile", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"),
                     help="form of the headline tube (fp64 is for profiling runs; the headline is fp32)")
-    ap.add_argument("--legs", default="fp64,batched,adjoint,ballistic,high,plane,copy,cpu",
-                    help="comma-separated extra legs (fp64, batched, adjoint, ballistic, high, plane, copy, "
-                         "cpu) or 'none'")
+    ap.add_argument("--legs", default="fp64,tau,batched,adjoint,ballistic,high,plane,copy,stream,cpu",
+                    help="comma-separated extra legs (fp64, tau, batched, adjoint, ballistic, high, plane, copy, "
+                         "stream, cpu) or 'none'")
     ap.add_argument("--plane-steps", type=int, default=20)
     ap.add_argument("--high-steps", type=int, default=20)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--ballistic-steps", type=int, default=20)
+    ap.add_argument("--ballistic-full-steps", type=int, default=4000,
+                    help="steps of the ballistic run checked against eq. ballistic (0: skip)")
+    ap.add_argument("--tau-steps", type=int, default=2000)
+    ap.add_argument("--batched-schedule", default="",
+                    help="tile,persistent,blocks_per_cu,graph_steps for the batched leg instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1); the multi-GPU "
@@ -452,9 +719,12 @@ def main():
     torch.cuda.set_device(0)
     params = dict(nx=args.nx, q_xi=64, q_p=4, tau=1e-2)
     sched = dict(tile=args.tile)
-    r32, f32, lat = leg_single(args.precision, params, args.steps, args.warmup, sched)
+    key = f"sod_large/{args.precision}" if args.nx == 1 << 20 else None
+    r32, f32, lat, win32 = leg_single(args.precision, params, args.steps, args.warmup, sched, key)
     del lat
     torch.cuda.empty_cache()
+    progress("headline done")
+    windows = [win32]
     line = {
         "metric": "cell*quad-point updates/s (FP32 vs FP64) + % HBM roofline; adjoint steps/s",
         "value": r32["value"],
@@ -473,33 +743,80 @@ def main():
                    "nx": params["nx"], "q_xi": 64, "q_p": 4, "tau": 1e-2, "schedule": r32["schedule"]},
         "roofline": r32["roofline"],
     }
+    legs_out = {}
     if "fp64" in legs:
-        r64, f64, lat = leg_single("fp64", params, args.steps, args.warmup, sched)
+        r64, f64, lat, win64 = leg_single("fp64", params, args.steps, args.warmup, sched,
+                                          "sod_large/fp64" if args.nx == 1 << 20 else None)
         del lat
         torch.cuda.empty_cache()
+        windows.append(win64)
         line["fp64"] = dict(value=r64["value"], ms_per_step=r64["ms_per_step"], roofline=r64["roofline"],
                             speedup_fp32_over_fp64=r32["value"] / r64["value"])
         line["fp32_vs_fp64_error"] = dict(after_steps=args.steps + args.warmup, fields=error_table(f32, f64))
+        progress("fp64 done")
+    if "tau" in legs:
+        line["tau_sweep"] = leg_tau_sweep(args.tau_steps)
     if "batched" in legs:
-        line["batched"] = leg_batched(args.batched_steps)
+        bs = None
+        if args.batched_schedule:
+            v = [int(x) for x in args.batched_schedule.split(",")]
+            bs = dict(tile=v[0], persistent=v[1], blocks_per_cu=v[2], graph_steps=v[3])
+        line["batched"], wins = leg_batched(args.batched_steps, bs)
+        windows += wins
+        progress("batched done")
     if "adjoint" in legs:
-        line["adjoint"] = dict(fp64=leg_adjoint("fp64"), fp32=leg_adjoint("fp32"))
+        line["adjoint"] = dict(fp64=leg_adjoint("fp64", fd=True), fp32=leg_adjoint("fp32"))
+        g64, g32 = line["adjoint"]["fp64"], line["adjoint"]["fp32"]
+        line["adjoint"]["fp32_vs_fp64_rel"] = dict(tau=abs(g32["grad_tau"] - g64["grad_tau"]) / abs(g64["grad_tau"]),
+                                                   P_L=abs(g32["grad_P_L"] - g64["grad_P_L"]) / abs(g64["grad_P_L"]))
+        progress("adjoint done")
     if "ballistic" in legs:
-        line["ballistic"] = leg_ballistic(args.ballistic_steps)
+        line["ballistic"], win = leg_ballistic(args.ballistic_steps, full_steps=args.ballistic_full_steps)
+        windows.append(win)
     if "high" in legs:
-        h32, hf32 = leg_high_order("fp32", args.high_steps)
-        h64, hf64 = leg_high_order("fp64", args.high_steps)
+        h32, hf32, w32 = leg_high_order("fp32", args.high_steps)
+        h64, hf64, w64 = leg_high_order("fp64", args.high_steps)
+        windows += [w32, w64]
         line["high_order"] = dict(fp32=h32, fp64=h64, fp32_vs_fp64_error=dict(
             after_steps=args.high_steps + 2, fields=error_table(hf32, hf64)))
+        progress("high-order done")
     if "plane" in legs:
-        p32, pf32 = leg_plane("fp32", args.plane_steps)
-        p64, pf64 = leg_plane("fp64", args.plane_steps)
+        p32, pf32, w32 = leg_plane("fp32", args.plane_steps)
+        p64, pf64, w64 = leg_plane("fp64", args.plane_steps)
+        windows += [w32, w64]
         line["plane"] = dict(fp32=p32, fp64=p64, fp32_vs_fp64_error=dict(
             after_steps=args.plane_steps + 2, fields=plane_error_table(pf32, pf64)))
+        progress("plane done")
     if "copy" in legs:
         line["copy"] = leg_copy()
+    if "stream" in legs:
+        line["stream"] = leg_stream()
+        # the stage kernel against its own memory pattern with no arithmetic
+        st = line["stream"][args.precision]
+        line["roofline"]["stream_step_us"] = st["step_us"]
+        line["roofline"]["frac_of_stream"] = round(st["step_us"] / (3 * line["roofline"]["launch_us"]), 4)
+        if "fp64" in line:
+            line["fp64"]["roofline"]["frac_of_stream"] = round(
+                line["stream"]["fp64"]["step_us"] / (3 * line["fp64"]["roofline"]["launch_us"]), 4)
+        progress("copy/stream done")
     if "cpu" in legs:
-        line["cpu_baseline"] = cpu_baseline(params)
+        line["cpu_baseline"], errors = cpu_baseline(params, windows)
+        # every result's max and L2 errors against the FP64 oracle
+        for name, err in errors.items():
+            leg, form = name.split("/")
+            if leg == "sod_large" and form == args.precision:
+                line["oracle_error"] = err
+            elif leg == "sod_large":
+                line.setdefault("fp64", {})["oracle_error"] = err
+            elif leg == "sod_batched":
+                line.setdefault("batched", {}).setdefault("oracle_error", {})[form] = err
+            elif leg == "sod_ballistic":
+                line.setdefault("ballistic", {})["oracle_error"] = err
+            elif leg == "sod_large_high_order":
+                line.setdefault("high_order", {}).setdefault(form, {})["oracle_error"] = err
+            elif leg == "plane_quadrants":
+                line.setdefault("plane", {}).setdefault(form, {})["oracle_error"] = err
+        progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 
 

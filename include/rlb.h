@@ -289,6 +289,14 @@ rlb_status rlb_step_noalloc(rlb_lattice* lat, void* state, int64_t nsteps, uint3
 
 /* Plain device copy kernel (bandwidth calibration); asynchronous. */
 rlb_status rlb_device_copy(void* dst, const void* src, size_t bytes, void* hip_stream);
+/* Streaming probe with the stage kernel's memory pattern (256-column tiles
+ * walking the rows of [rows][ld] matrices in chunks, the same cache policies
+ * and buffer accesses) and no arithmetic but one add: out = a + b, or out = a
+ * when b is NULL (the one-read, one-write pattern of the first Runge-Kutta
+ * stage).  The practical HBM ceiling of the stage kernel; elem_bytes 4 or 8;
+ * device buffers, caller-owned; asynchronous. */
+rlb_status rlb_device_stream(void* out, const void* a, const void* b, int64_t rows, int64_t ld, int32_t cols,
+                             int32_t elem_bytes, void* hip_stream);
 
 const char* rlb_status_string(rlb_status st);
 const char* rlb_last_error(const rlb_lattice* lat);

@@ -1264,6 +1264,17 @@ rlb_status rlb_device_copy(void* dst, const void* src, size_t bytes, void* hip_s
   return e == hipSuccess ? RLB_OK : RLB_ERR_HIP;
 }
 
+rlb_status rlb_device_stream(void* out, const void* a, const void* b, int64_t rows, int64_t ld, int32_t cols,
+                             int32_t elem_bytes, void* hip_stream) {
+  if (!out || !a || rows < 1 || cols < 1 || ld < cols || (elem_bytes != 4 && elem_bytes != 8)) return RLB_ERR_INVALID_ARG;
+  // one chunk of rows is addressed with 32-bit byte offsets, as in the stage kernel
+  if (rows > (int64_t(1) << 24) || ld * elem_bytes * 8 > (int64_t(1) << 31)) return RLB_ERR_INVALID_ARG;
+  const uintptr_t al = reinterpret_cast<uintptr_t>(out) | reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b);
+  if (al % uintptr_t(elem_bytes)) return RLB_ERR_INVALID_ARG;
+  const hipError_t e = launch_stream(out, a, b, int(rows), ld, cols, elem_bytes, static_cast<hipStream_t>(hip_stream));
+  return e == hipSuccess ? RLB_OK : RLB_ERR_HIP;
+}
+
 const char* rlb_status_string(rlb_status st) {
   switch (st) {
     case RLB_OK: return "ok";

@@ -193,6 +193,8 @@ hipError_t launch_fields(const TubeDev* tubes, int tube, int nx, const double* r
 hipError_t launch_totals(const TubeDev* tubes, int tube, const double* rec, double* out, hipStream_t stream);
 hipError_t launch_copy(void* dst, const void* src, size_t bytes, hipStream_t stream);
 hipError_t launch_fill_u32(unsigned* p, int n, unsigned v, hipStream_t stream);
+hipError_t launch_stream(void* out, const void* a, const void* b, int rows, int64_t ld, int cols, int elem_bytes,
+                         hipStream_t stream);
 hipError_t launch_feq(int prec_fp32, const LaunchShape& ls, const void* args, hipStream_t stream);
 hipError_t launch_combine(const TubeDev* tubes, const WorkItem* items, int nitems, int tile, const double* itab,
                           const double* part, int part_stride, double* rec_out, hipStream_t stream);

@@ -608,6 +608,58 @@ __global__ __launch_bounds__(256) void copy_kernel(uint4* __restrict__ dst, cons
   for (size_t k = size_t(blockIdx.x) * blockDim.x + threadIdx.x; k < n16; k += stride) dst[k] = src[k];
 }
 
+// Streaming probe with the stage kernel's memory pattern and no arithmetic
+// beyond one add: workgroups of 256 lanes own 256-column tiles of a [rows][ld]
+// matrix (XCD-mapped like the stage kernel) and walk its rows in chunks of
+// CH, the next chunk's loads issued before the current one is stored;
+// out = a (+ b), with a at the default cache policy and b and out
+// non-temporal, as f_k, f^n and the stage output.  The practical ceiling of
+// the stage kernel's traffic: b = nullptr is stage 1 (one read, one write),
+// otherwise stages 2 and 3 (two reads, one write).
+template <typename Real, bool TWO>
+__global__ __launch_bounds__(256) void stream_kernel(Real* out, const Real* a, const Real* b, int rows, int64_t ld,
+                                                     int cols) {
+  constexpr int CH = chunk_points<Real>();
+  const int ntiles = (cols + 255) / 256;
+  const bool xcd_map = (gridDim.x % kXcds) == 0 || int(gridDim.x) == ntiles;
+  const uint32_t row_bytes = uint32_t(ld) * uint32_t(sizeof(Real));
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+    const int tile = xcd_map ? xcd_item(v, ntiles) : v;
+    const int x = tile * 256 + int(threadIdx.x);
+    const int xc = min(x, cols - 1);
+    const uint32_t vx = uint32_t(xc) * uint32_t(sizeof(Real));
+    Real ca[CH], cb[CH];
+    auto issue = [&](int r0, Real* da, Real* db) {
+      const int last = min(CH - 1, rows - 1 - r0);
+      const Rsrc ra = make_rsrc(a + int64_t(r0) * ld, uint32_t(CH) * row_bytes);
+#pragma unroll
+      for (int c = 0; c < CH; ++c) da[c] = BufIO<Real>::template load<kLoadAux>(ra, vx, uint32_t(min(c, last)) * row_bytes);
+      if (TWO) {
+        const Rsrc rb = make_rsrc(b + int64_t(r0) * ld, uint32_t(CH) * row_bytes);
+#pragma unroll
+        for (int c = 0; c < CH; ++c) db[c] = BufIO<Real>::template load<kFnAux>(rb, vx, uint32_t(min(c, last)) * row_bytes);
+      }
+    };
+    issue(0, ca, cb);
+    for (int r0 = 0; r0 < rows; r0 += CH) {
+      Real na[CH], nb[CH];
+      if (r0 + CH < rows) issue(r0 + CH, na, nb);
+      const Rsrc ro = make_rsrc(out + int64_t(r0) * ld, uint32_t(CH) * row_bytes);
+#pragma unroll
+      for (int c = 0; c < CH; ++c)
+        if (r0 + c < rows && x < cols)
+          BufIO<Real>::template store<kStoreAux>(TWO ? ca[c] + cb[c] : ca[c], ro, vx, uint32_t(c) * row_bytes);
+      if (r0 + CH < rows) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          ca[c] = na[c];
+          cb[c] = nb[c];
+        }
+      }
+    }
+  }
+}
+
 // Fills n words with v (flags and counters; a kernel rather than a memset so
 // that the clear can sit in captured work).
 __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, int n, unsigned v) {
@@ -706,6 +758,27 @@ hipError_t launch_combine(const TubeDev* tubes, const WorkItem* items, int nitem
                           const double* part, int part_stride, double* rec_out, hipStream_t stream) {
   hipLaunchKernelGGL(combine_kernel, dim3(nitems), dim3(256), 0, stream, tubes, items, nitems, tile, itab, part,
                      part_stride, rec_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream(void* out, const void* a, const void* b, int rows, int64_t ld, int cols, int elem_bytes,
+                         hipStream_t stream) {
+  const int ntiles = (cols + 255) / 256;
+  if (elem_bytes == 4) {
+    if (b)
+      hipLaunchKernelGGL((stream_kernel<float, true>), dim3(ntiles), dim3(256), 0, stream, static_cast<float*>(out),
+                         static_cast<const float*>(a), static_cast<const float*>(b), rows, ld, cols);
+    else
+      hipLaunchKernelGGL((stream_kernel<float, false>), dim3(ntiles), dim3(256), 0, stream, static_cast<float*>(out),
+                         static_cast<const float*>(a), static_cast<const float*>(b), rows, ld, cols);
+  } else {
+    if (b)
+      hipLaunchKernelGGL((stream_kernel<double, true>), dim3(ntiles), dim3(256), 0, stream, static_cast<double*>(out),
+                         static_cast<const double*>(a), static_cast<const double*>(b), rows, ld, cols);
+    else
+      hipLaunchKernelGGL((stream_kernel<double, false>), dim3(ntiles), dim3(256), 0, stream, static_cast<double*>(out),
+                         static_cast<const double*>(a), static_cast<const double*>(b), rows, ld, cols);
+  }
   return hipGetLastError();
 }
 

@@ -95,6 +95,7 @@ _SIGNATURES = {
     "rlb_tube_info": [_VP, ctypes.c_int32, _DP, _DP, ctypes.POINTER(ctypes.c_int32)],
     "rlb_tables": [_VP, ctypes.c_int32, _DP, _DP, _DP, _DP],
     "rlb_device_copy": [_VP, _VP, ctypes.c_size_t, _VP],
+    "rlb_device_stream": [_VP, _VP, _VP, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _VP],
     "rlb_adjoint_step": [_VP, _VP, _VP, _VP],
     "rlb_adjoint_segment_size": [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "rlb_adjoint_segment": [_VP, _VP, ctypes.c_int32, _VP, ctypes.c_size_t, _VP, _VP],
@@ -418,6 +419,18 @@ def device_copy(dst, src, nbytes: int, stream=None):
     st = lib.rlb_device_copy(_VP(dst.data_ptr()), _VP(src.data_ptr()), nbytes, _VP(stream.cuda_stream))
     if st != RLB_OK:
         raise RLBError(st, "device copy failed")
+
+
+def device_stream(out, a, b, rows: int, ld: int, cols: int, stream=None):
+    """out = a (+ b) over [rows][ld] matrices with the stage kernel's memory
+    pattern (rlb_device_stream); b may be None."""
+    torch = _torch()
+    lib = load_library()
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    st = lib.rlb_device_stream(_VP(out.data_ptr()), _VP(a.data_ptr()), _VP(b.data_ptr()) if b is not None else None,
+                               int(rows), int(ld), int(cols), out.element_size(), _VP(stream.cuda_stream))
+    if st != RLB_OK:
+        raise RLBError(st, "device stream failed")
 
 
 PLANE_FIELDS = ("N0", "Nx", "Nz", "T00", "T0x", "T0z", "Txx", "Txz", "Tzz", "e", "n", "vx", "vz", "T")

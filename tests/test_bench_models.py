@@ -48,7 +48,46 @@ def test_high_order_flops(q_xi, n_v, pairs):
     assert bench.high_order_flops(t) == 4 * ((q_xi + 1) // 2) * pairs * 1000 * 4
 
 
-def test_cpu_baseline_record():
-    r = bench.cpu_baseline(dict(nx=1 << 20, q_xi=8, q_p=3, tau=1e-2), target_s=0.05)
-    assert r["kind"] == "oracle" and r["cores"] >= 1 and r["value"] > 0
+def test_cpu_baseline_record_and_oracle_windows():
+    # a window request whose "GPU" result is the oracle's own full-tube run:
+    # the window evolves exactly like the full tube, so the errors vanish
+    import numpy as np
+    from oracle import oracle as O
+    params = dict(nx=640, q_xi=8, q_p=3, tau=1e-2)
+    t = O.Tube(**params)
+    full = O.fields(t, O.run(t, bench.SOD_L, bench.SOD_R, 6))
+    win = bench.window_request("sod_large/fp64", params, bench.SOD_L, bench.SOD_R, 6, t.step_dt, full, half=32)
+    assert (win["a"], win["b"], win["lo"], win["hi"]) == (320 - 32 - 54, 320 + 32 + 54, 288, 352)
+    r, errs = bench.cpu_baseline(dict(nx=1 << 20, q_xi=8, q_p=3, tau=1e-2), [win], target_s=0.05)
+    assert r["kind"] == "oracle" and r["cores"] >= 1 and r["value"] > 0 and r["cpu"]
     assert r["unit"] == "cell*quad-point updates/s" and "steps in" in r["sample"]
+    e = errs["sod_large/fp64"]
+    assert max(v["max"] for k, v in e.items() if isinstance(v, dict)) < 1e-14
+    # a short tube is taken whole
+    short = dict(nx=100, q_xi=8, q_p=3, tau=1e-2)
+    w2 = bench.window_request("x/fp32", short, bench.SOD_L, bench.SOD_R, 6, 0.005, np.zeros((10, 100)))
+    assert (w2["a"], w2["b"], w2["lo"], w2["hi"]) == (0, 100, 0, 100)
+
+
+def test_ballistic_profile_and_staircase_bound():
+    # worked values of eq. ballistic (n_L = 1, n_R = 0.125) and the quadrature
+    # staircase bound of a 64-node Gauss-Legendre rule
+    import numpy as np
+    nb = bench.n_ballistic(np.array([0.0, 0.5, -0.5]), 1.0)
+    assert np.allclose(nb, [0.518222623493031, 0.302072108268456, 0.763829207738058], rtol=0, atol=1e-14)
+    assert bench.n_ballistic(np.array([-2.0, 2.0]), 1.0).tolist() == [1.0, 0.125]
+    xi, w = np.polynomial.legendre.leggauss(64)
+    assert abs(bench.staircase_bound(xi, w) - 0.01346) < 2e-4
+    xi, w = np.polynomial.legendre.leggauss(256)
+    assert abs(bench.staircase_bound(xi, w) - 0.00338) < 1e-4
+
+
+def test_error_table_fields():
+    import numpy as np
+    b = np.ones((10, 50))
+    b[7] = 0.5  # v
+    a = b.copy()
+    a[5, 3] += 1e-6
+    e = bench.error_table(a, b)
+    assert abs(e["e"]["max"] - 1e-6) < 1e-12 and e["T00"]["max"] == 0 and e["u"]["max"] == 0
+    assert set(e) == {"e", "u", "T00", "T0z", "Tzz", "N0", "n"}
