@@ -113,6 +113,14 @@ def _load():
         lib.oracle_plane_step.argtypes = [pp, dp, ctypes.c_int64]
         lib.oracle_plane_rhs.argtypes = [pp, dp, dp]
         lib.oracle_plane_fields.argtypes = [pp, dp, dp]
+        bp = ctypes.POINTER(_Box)
+        lib.oracle_box_tables.argtypes = [bp, dp, dp]
+        lib.oracle_landau3d.argtypes = [dp, dp]
+        lib.oracle_box_feq_nodes.argtypes = [bp] + [ctypes.c_double] * 5 + [dp]
+        lib.oracle_box_init.argtypes = [bp, dp, dp]
+        lib.oracle_box_step.argtypes = [bp, dp, ctypes.c_int64]
+        lib.oracle_box_rhs.argtypes = [bp, dp, dp]
+        lib.oracle_box_fields.argtypes = [bp, dp, dp]
         _lib = lib
     return _lib
 
@@ -405,3 +413,162 @@ def plane_moments_weights(plane: Plane) -> np.ndarray:
 
 def plane_run(plane: Plane, fields: np.ndarray, nsteps: int) -> np.ndarray:
     return plane_step(plane, plane_init(plane, fields), nsteps)
+
+
+# ---------------------------------------------------------------------------
+# Three-dimensional box, any flow direction (full azimuthal node set)
+# ---------------------------------------------------------------------------
+class _Box(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("x_min", ctypes.c_double), ("x_max", ctypes.c_double),
+                ("y_min", ctypes.c_double), ("y_max", ctypes.c_double),
+                ("z_min", ctypes.c_double), ("z_max", ctypes.c_double),
+                ("q_xi", ctypes.c_int32), ("q_phi", ctypes.c_int32), ("q_p", ctypes.c_int32),
+                ("n_v", ctypes.c_int32), ("n_p", ctypes.c_int32),
+                ("tau", ctypes.c_double), ("dt", ctypes.c_double), ("T0", ctypes.c_double),
+                ("weno_eps", ctypes.c_double)]
+
+
+BOX_FIELDS = ("N0", "Nx", "Ny", "Nz", "T00", "T0x", "T0y", "T0z", "Txx", "Txy", "Txz", "Tyy", "Tyz", "Tzz",
+              "e", "n", "vx", "vy", "vz", "T")
+
+
+@dataclass
+class Box:
+    """An (x, y, z) box with the full momentum quadrature Q_p x Q_xi x Q_phi
+    (every azimuthal node evolved).
+
+    ``dt`` defaults to ``min(cfl / (1/dx + 1/dy + 1/dz), dt_tau_max * tau)``.
+    """
+    nx: int = 8
+    ny: int = 8
+    nz: int = 8
+    q_xi: int = 6
+    q_phi: int = 8
+    q_p: int = 3
+    n_v: int = 5
+    n_p: int = 2
+    tau: float = 1e-2
+    x_min: float = -0.5
+    x_max: float = 0.5
+    y_min: float = -0.5
+    y_max: float = 0.5
+    z_min: float = -0.5
+    z_max: float = 0.5
+    cfl: float = 0.5
+    dt_tau_max: float = 0.5
+    dt: float = 0.0
+    T0: float = 1.0
+    weno_eps: float = 1e-6
+
+    @property
+    def dx(self) -> float:
+        return (self.x_max - self.x_min) / self.nx
+
+    @property
+    def dy(self) -> float:
+        return (self.y_max - self.y_min) / self.ny
+
+    @property
+    def dz(self) -> float:
+        return (self.z_max - self.z_min) / self.nz
+
+    @property
+    def step_dt(self) -> float:
+        if self.dt > 0:
+            return self.dt
+        return min(self.cfl / (1.0 / self.dx + 1.0 / self.dy + 1.0 / self.dz), self.dt_tau_max * self.tau)
+
+    @property
+    def Q(self) -> int:
+        return self.q_p * self.q_xi * self.q_phi
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def centres(self):
+        x = self.x_min + (np.arange(self.nx) + 0.5) * self.dx
+        y = self.y_min + (np.arange(self.ny) + 0.5) * self.dy
+        z = self.z_min + (np.arange(self.nz) + 0.5) * self.dz
+        return x, y, z
+
+    def _c(self) -> _Box:
+        return _Box(self.nx, self.ny, self.nz, self.x_min, self.x_max, self.y_min, self.y_max, self.z_min, self.z_max,
+                    self.q_xi, self.q_phi, self.q_p, self.n_v, self.n_p, self.tau, self.step_dt, self.T0,
+                    self.weno_eps)
+
+
+def box_tables(box: Box):
+    """(cos phi_k, sin phi_k) of the azimuthal nodes."""
+    c = np.zeros(box.q_phi); s = np.zeros(box.q_phi)
+    _check(_load().oracle_box_tables(ctypes.byref(box._c()), _ptr(c), _ptr(s)))
+    return c, s
+
+
+def landau3d(m):
+    """Landau frame of the 14 moments -> (e, v_x, v_y, v_z, gamma, n, T)."""
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    out = np.zeros(7)
+    _load().oracle_landau3d(_ptr(m), _ptr(out))
+    return out
+
+
+def box_feq_nodes(box: Box, n: float, T: float, ux: float, uy: float, uz: float) -> np.ndarray:
+    F = np.zeros(box.Q)
+    _check(_load().oracle_box_feq_nodes(ctypes.byref(box._c()), n, T, ux, uy, uz, _ptr(F)))
+    return F
+
+
+def box_init(box: Box, fields: np.ndarray) -> np.ndarray:
+    """F[Q, nz, ny, nx] from per-cell states fields[5, nz, ny, nx] = P, n, u^x, u^y, u^z."""
+    f = np.ascontiguousarray(fields, dtype=np.float64)
+    assert f.shape == (5, box.nz, box.ny, box.nx)
+    F = np.zeros((box.Q, box.nz, box.ny, box.nx))
+    _check(_load().oracle_box_init(ctypes.byref(box._c()), _ptr(f), _ptr(F)))
+    return F
+
+
+def box_step(box: Box, F: np.ndarray, nsteps: int) -> np.ndarray:
+    G = np.array(F, dtype=np.float64, order="C", copy=True)
+    _check(_load().oracle_box_step(ctypes.byref(box._c()), _ptr(G), int(nsteps)))
+    return G
+
+
+def box_rhs(box: Box, F: np.ndarray) -> np.ndarray:
+    G = np.ascontiguousarray(F, dtype=np.float64)
+    out = np.zeros_like(G)
+    _check(_load().oracle_box_rhs(ctypes.byref(box._c()), _ptr(G), _ptr(out)))
+    return out
+
+
+def box_fields(box: Box, F: np.ndarray) -> np.ndarray:
+    """Fields [20, nz, ny, nx]: the 14 moments, e, n, v_x, v_y, v_z, T."""
+    G = np.ascontiguousarray(F, dtype=np.float64)
+    out = np.zeros((20, box.nz, box.ny, box.nx))
+    _check(_load().oracle_box_fields(ctypes.byref(box._c()), _ptr(G), _ptr(out)))
+    return out
+
+
+def box_run(box: Box, fields: np.ndarray, nsteps: int) -> np.ndarray:
+    return box_step(box, box_init(box, fields), nsteps)
+
+
+def box_moments_weights(box: Box) -> np.ndarray:
+    """Moment basis B[14, Q]: the 14 moments of a cell = B @ F[:, cell]."""
+    xi, wxi, p, wp = tables(Tube(nx=1, q_xi=box.q_xi, q_p=box.q_p, n_v=box.n_v, n_p=box.n_p, T0=box.T0))
+    cphi, sphi = box_tables(box)
+    B = np.zeros((14, box.Q))
+    t3, t4 = box.T0 ** 3, box.T0 ** 4
+    for i in range(box.q_p):
+        for j in range(box.q_xi):
+            st = math.sqrt(1.0 - xi[j] ** 2)
+            for k in range(box.q_phi):
+                s = (i * box.q_xi + j) * box.q_phi + k
+                w = wp[i] * wxi[j] / box.q_phi
+                v = (st * cphi[k], st * sphi[k], xi[j])
+                row = [t3 * p[i]] + [t3 * p[i] * v[a] for a in range(3)] + [t4 * p[i] ** 2] + \
+                      [t4 * p[i] ** 2 * v[a] for a in range(3)] + \
+                      [t4 * p[i] ** 2 * v[a] * v[b] for a in range(3) for b in range(a, 3)]
+                B[:, s] = w * np.array(row)
+    return B

@@ -890,3 +890,304 @@ int oracle_plane_fields(const oracle_plane* p, const double* F, double* out) {
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Multi-dimensional model on a box (x, y, z), any flow direction.
+//
+// eq. Boltz_gen with v = (sin(theta) cos(phi), sin(theta) sin(phi), cos(theta))
+// resolved in all three directions:
+//   dF/dt = -v_x dF/dx - v_y dF/dy - v_z dF/dz
+//           - ((u^0 - v_x u^x - v_y u^y - v_z u^z)/tau) (F - F^eq),
+// on the full product quadrature: Gauss-Laguerre in p, Gauss-Legendre in
+// xi = cos(theta) and every node of the trapezoid rule in phi (eq.
+// azimuthInt), phi_k = 2 pi k / Q_phi, k = 0 .. Q_phi - 1, weight 1/Q_phi of
+// the phi-average [reading: the printed nodes are garbled; a periodic
+// trapezoid grid is exact below Q_phi].  No node is collapsed: the velocity
+// may point anywhere.  F keeps the 1D normalisation (2 pi e^p f), so a box
+// varying along z only with u along z reproduces the tube, and one with
+// ny = 1 and u^y = 0 reproduces the plane.
+//
+// Point s = (i * Q_xi + j) * Q_phi + k; F[s][z][y][x].  Moments per cell (14):
+//   N0, Nx, Ny, Nz = T0^3 sum w p {1, v_x, v_y, v_z} F
+//   T00, T0x, T0y, T0z, Txx, Txy, Txz, Tyy, Tyz, Tzz
+//                  = T0^4 sum w p^2 {1, v_i, v_i v_j} F
+// with w = w_p w_xi / Q_phi.  Landau frame: the timelike eigenvector of
+// T^mu_nu by the power method (as for the plane, three velocity components).
+// Equilibrium: the Legendre series in c = v . u_hat with the 1D coefficients
+// at the speed |u| (Funk-Hecke, as for the plane) [reading].
+// ===========================================================================
+
+extern "C" {
+struct oracle_box {
+  int32_t nx, ny, nz;       // cells along x, y and z, cell-centred
+  double x_min, x_max, y_min, y_max, z_min, z_max;
+  int32_t q_xi, q_phi, q_p; // quadrature orders
+  int32_t n_v, n_p;         // truncation orders
+  double tau, dt, T0, weno_eps;
+};
+}
+
+namespace {
+
+struct BoxTables {
+  Tables t1;
+  int qf;
+  std::vector<double> cphi, sphi, sth;
+  static oracle_tube as_tube(const oracle_box& b) {
+    oracle_tube t;
+    std::memset(&t, 0, sizeof t);
+    t.nx = b.nz;
+    t.z_min = b.z_min;
+    t.z_max = b.z_max;
+    t.q_xi = b.q_xi;
+    t.q_p = b.q_p;
+    t.n_v = b.n_v;
+    t.n_p = b.n_p;
+    t.tau = b.tau;
+    t.dt = b.dt;
+    t.T0 = b.T0;
+    t.weno_eps = b.weno_eps;
+    return t;
+  }
+  explicit BoxTables(const oracle_box& b) : t1(as_tube(b)), qf(b.q_phi) {
+    const long double pi = 3.141592653589793238462643383279502884L;
+    cphi.resize(qf);
+    sphi.resize(qf);
+    for (int k = 0; k < qf; ++k) {
+      cphi[k] = double(std::cos(2.0L * pi * k / qf));
+      sphi[k] = double(std::sin(2.0L * pi * k / qf));
+    }
+    sth.resize(t1.qx);
+    for (int j = 0; j < t1.qx; ++j) sth[j] = std::sqrt(1.0 - t1.xi[j] * t1.xi[j]);
+  }
+  int Q() const { return t1.qp * t1.qx * qf; }
+  double vx(int j, int k) const { return sth[j] * cphi[k]; }
+  double vy(int j, int k) const { return sth[j] * sphi[k]; }
+  double vz(int j) const { return t1.xi[j]; }
+};
+
+struct Macro3 {
+  double e, v[3], gamma, u[3], n, T;
+};
+
+// Moments of one cell: m = N0, Nx, Ny, Nz, T00, T0x, T0y, T0z, Txx, Txy, Txz,
+// Tyy, Tyz, Tzz.
+void box_moments(const BoxTables& bt, const double* F, int64_t cells, int64_t c, double m[14]) {
+  for (int a = 0; a < 14; ++a) m[a] = 0.0;
+  const Tables& tb = bt.t1;
+  const double t3 = tb.T0 * tb.T0 * tb.T0, t4 = t3 * tb.T0;
+  for (int i = 0; i < tb.qp; ++i)
+    for (int j = 0; j < tb.qx; ++j)
+      for (int k = 0; k < bt.qf; ++k) {
+        const int s = (i * tb.qx + j) * bt.qf + k;
+        const double f = tb.wp[i] * tb.wxi[j] / bt.qf * F[s * cells + c];
+        const double v[3] = {bt.vx(j, k), bt.vy(j, k), bt.vz(j)}, p = tb.p[i];
+        m[0] += t3 * p * f;
+        for (int a = 0; a < 3; ++a) m[1 + a] += t3 * p * v[a] * f;
+        m[4] += t4 * p * p * f;
+        for (int a = 0; a < 3; ++a) m[5 + a] += t4 * p * p * v[a] * f;
+        int q = 8;
+        for (int a = 0; a < 3; ++a)
+          for (int b = a; b < 3; ++b) m[q++] += t4 * p * p * v[a] * v[b] * f;
+      }
+}
+
+// Spatial tensor T^{ab} of the 14 moments.
+inline long double box_Tij(const double m[14], int a, int b) {
+  if (a > b) std::swap(a, b);
+  static const int idx[3][3] = {{8, 9, 10}, {9, 11, 12}, {10, 12, 13}};
+  return m[idx[a][b]];
+}
+
+// Landau frame by the power method on T^mu_nu (extended precision): with
+// u = gamma (1, v), one step is v_i <- (T^{0i} - T^{ij} v_j) / (T^{00} - T^{0j} v_j).
+Macro3 landau3(const double m[14]) {
+  typedef long double E;
+  const E N0 = m[0], T00 = m[4];
+  const E N[3] = {m[1], m[2], m[3]}, T0[3] = {m[5], m[6], m[7]};
+  E v[3] = {0, 0, 0};
+  for (int it = 0; it < 1000000; ++it) {
+    const E e = T00 - T0[0] * v[0] - T0[1] * v[1] - T0[2] * v[2];
+    E nv[3];
+    for (int a = 0; a < 3; ++a) {
+      E r = T0[a];
+      for (int b = 0; b < 3; ++b) r -= box_Tij(m, a, b) * v[b];
+      nv[a] = r / e;
+    }
+    const E d = std::fabs(nv[0] - v[0]) + std::fabs(nv[1] - v[1]) + std::fabs(nv[2] - v[2]);
+    for (int a = 0; a < 3; ++a) v[a] = nv[a];
+    if (!(d > 1e-19L)) break;
+  }
+  Macro3 M;
+  const E e = T00 - T0[0] * v[0] - T0[1] * v[1] - T0[2] * v[2];
+  const E gamma = 1 / std::sqrt(1 - v[0] * v[0] - v[1] * v[1] - v[2] * v[2]);
+  const E n = gamma * (N0 - v[0] * N[0] - v[1] * N[1] - v[2] * N[2]);
+  M.e = double(e);
+  for (int a = 0; a < 3; ++a) {
+    M.v[a] = double(v[a]);
+    M.u[a] = double(gamma * v[a]);
+  }
+  M.gamma = double(gamma);
+  M.n = double(n);
+  M.T = double(e / (3 * n));
+  return M;
+}
+
+// Truncated equilibrium at every point of the box's quadrature.
+void box_feq_nodes(const BoxTables& bt, double n, double T, const double u[3], double* Feq) {
+  const Tables& tb = bt.t1;
+  const double ua = std::sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]), gamma = std::sqrt(1.0 + ua * ua);
+  const double h[3] = {ua > 0.0 ? u[0] / ua : 0.0, ua > 0.0 ? u[1] / ua : 0.0, ua > 0.0 ? u[2] / ua : 1.0};
+  std::vector<double> C((tb.nv + 1) * (tb.np + 1));
+  feq_coefficients(tb, n, T, gamma, ua, C.data());
+  for (int i = 0; i < tb.qp; ++i)
+    for (int j = 0; j < tb.qx; ++j)
+      for (int k = 0; k < bt.qf; ++k) {
+        const double c = bt.vx(j, k) * h[0] + bt.vy(j, k) * h[1] + bt.vz(j) * h[2];
+        double acc = 0.0;
+        for (int l = 0; l <= tb.np; ++l)
+          for (int kk = 0; kk <= tb.nv; ++kk)
+            acc += (2.0 * kk + 1.0) / 2.0 / (l + 1.0) * legendre_P(kk, c) * tb.Ll[i * (tb.np + 1) + l] *
+                   C[kk * (tb.np + 1) + l];
+        Feq[(i * tb.qx + j) * bt.qf + k] = acc;
+      }
+}
+
+void box_rhs(const BoxTables& bt, const oracle_box& bx, const double* F, double* out) {
+  const int64_t nx = bx.nx, ny = bx.ny, nz = bx.nz, cells = nx * ny * nz;
+  const double dx = (bx.x_max - bx.x_min) / bx.nx, dy = (bx.y_max - bx.y_min) / bx.ny,
+               dz = (bx.z_max - bx.z_min) / bx.nz;
+  const double tau_inv = 1.0 / bx.tau;
+  const Tables& tb = bt.t1;
+  const int Q = bt.Q();
+#pragma omp parallel
+  {
+    std::vector<double> feq(Q);
+#pragma omp for schedule(static)
+    for (int64_t c = 0; c < cells; ++c) {
+      const int64_t x = c % nx, y = (c / nx) % ny, z = c / (nx * ny);
+      double m[14];
+      box_moments(bt, F, cells, c, m);
+      const Macro3 M = landau3(m);
+      box_feq_nodes(bt, M.n, M.T, M.u, feq.data());
+      for (int i = 0; i < tb.qp; ++i)
+        for (int j = 0; j < tb.qx; ++j)
+          for (int k = 0; k < bt.qf; ++k) {
+            const int s = (i * tb.qx + j) * bt.qf + k;
+            const double vx = bt.vx(j, k), vy = bt.vy(j, k), vz = bt.vz(j);
+            const double* pt = F + s * cells;
+            const double* row_x = pt + (z * ny + y) * nx;
+            const double* row_y = pt + z * nx * ny + x;
+            const double* row_z = pt + y * nx + x;
+            const double hxr = face_value_line(row_x, nx, 1, x, vx, bx.weno_eps);
+            const double hxl = face_value_line(row_x, nx, 1, x - 1, vx, bx.weno_eps);
+            const double hyr = face_value_line(row_y, ny, nx, y, vy, bx.weno_eps);
+            const double hyl = face_value_line(row_y, ny, nx, y - 1, vy, bx.weno_eps);
+            const double hzr = face_value_line(row_z, nz, nx * ny, z, vz, bx.weno_eps);
+            const double hzl = face_value_line(row_z, nz, nx * ny, z - 1, vz, bx.weno_eps);
+            const double adv = -vx / dx * (hxr - hxl) - vy / dy * (hyr - hyl) - vz / dz * (hzr - hzl);
+            const double rate = (M.gamma - vx * M.u[0] - vy * M.u[1] - vz * M.u[2]) * tau_inv;
+            out[s * cells + c] = adv - rate * (pt[c] - feq[s]);
+          }
+    }
+  }
+}
+
+void box_rk3_step(const BoxTables& bt, const oracle_box& bx, double* F, double* F1, double* F2, double* L) {
+  const int64_t N = int64_t(bt.Q()) * bx.nx * bx.ny * bx.nz;
+  const double dt = bx.dt;
+  box_rhs(bt, bx, F, L);
+  for (int64_t a = 0; a < N; ++a) F1[a] = F[a] + dt * L[a];
+  box_rhs(bt, bx, F1, L);
+  for (int64_t a = 0; a < N; ++a) F2[a] = 0.75 * F[a] + 0.25 * (F1[a] + dt * L[a]);
+  box_rhs(bt, bx, F2, L);
+  for (int64_t a = 0; a < N; ++a) F[a] = (1.0 / 3.0) * F[a] + (2.0 / 3.0) * (F2[a] + dt * L[a]);
+}
+
+bool box_valid(const oracle_box* b) {
+  return b && b->nx >= 1 && b->ny >= 1 && b->nz >= 1 && b->q_xi >= 1 && b->q_phi >= 1 && b->q_p >= 1 &&
+         b->n_v >= 0 && b->n_p >= 0 && b->tau > 0 && b->dt > 0 && b->T0 > 0 && b->x_max > b->x_min &&
+         b->y_max > b->y_min && b->z_max > b->z_min;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Azimuthal nodes of the box: cos(phi_k), sin(phi_k).
+int oracle_box_tables(const oracle_box* b, double* cphi, double* sphi) {
+  if (!box_valid(b)) return -1;
+  BoxTables bt(*b);
+  for (int k = 0; k < bt.qf; ++k) {
+    cphi[k] = bt.cphi[k];
+    sphi[k] = bt.sphi[k];
+  }
+  return 0;
+}
+
+// Landau frame of the 14 moments -> e, v_x, v_y, v_z, gamma, n, T.
+int oracle_landau3d(const double* m, double* out) {
+  const Macro3 M = landau3(m);
+  const double r[7] = {M.e, M.v[0], M.v[1], M.v[2], M.gamma, M.n, M.T};
+  for (int a = 0; a < 7; ++a) out[a] = r[a];
+  return 0;
+}
+
+int oracle_box_feq_nodes(const oracle_box* b, double n, double T, double ux, double uy, double uz, double* F) {
+  if (!box_valid(b)) return -1;
+  BoxTables bt(*b);
+  const double u[3] = {ux, uy, uz};
+  box_feq_nodes(bt, n, T, u, F);
+  return 0;
+}
+
+// Initial distribution from per-cell states fields[5][nz][ny][nx] = P, n, u^x, u^y, u^z.
+int oracle_box_init(const oracle_box* b, const double* fields, double* F) {
+  if (!box_valid(b)) return -1;
+  BoxTables bt(*b);
+  const int64_t cells = int64_t(b->nx) * b->ny * b->nz;
+  std::vector<double> feq(bt.Q());
+  for (int64_t c = 0; c < cells; ++c) {
+    const double P = fields[c], n = fields[cells + c];
+    const double u[3] = {fields[2 * cells + c], fields[3 * cells + c], fields[4 * cells + c]};
+    box_feq_nodes(bt, n, P / n, u, feq.data());
+    for (int s = 0; s < bt.Q(); ++s) F[s * cells + c] = feq[s];
+  }
+  return 0;
+}
+
+int oracle_box_step(const oracle_box* b, double* F, int64_t nsteps) {
+  if (!box_valid(b) || nsteps < 0) return -1;
+  BoxTables bt(*b);
+  const size_t N = size_t(bt.Q()) * b->nx * b->ny * b->nz;
+  std::vector<double> F1(N), F2(N), L(N);
+  for (int64_t n = 0; n < nsteps; ++n) box_rk3_step(bt, *b, F, F1.data(), F2.data(), L.data());
+  return 0;
+}
+
+int oracle_box_rhs(const oracle_box* b, const double* F, double* out) {
+  if (!box_valid(b)) return -1;
+  BoxTables bt(*b);
+  box_rhs(bt, *b, F, out);
+  return 0;
+}
+
+// Fields per cell [20][nz][ny][nx]: the 14 moments, e, n, v_x, v_y, v_z, T.
+int oracle_box_fields(const oracle_box* b, const double* F, double* out) {
+  if (!box_valid(b)) return -1;
+  BoxTables bt(*b);
+  const int64_t cells = int64_t(b->nx) * b->ny * b->nz;
+  for (int64_t c = 0; c < cells; ++c) {
+    double m[14];
+    box_moments(bt, F, cells, c, m);
+    const Macro3 M = landau3(m);
+    for (int a = 0; a < 14; ++a) out[a * cells + c] = m[a];
+    out[14 * cells + c] = M.e;
+    out[15 * cells + c] = M.n;
+    for (int a = 0; a < 3; ++a) out[(16 + a) * cells + c] = M.v[a];
+    out[19 * cells + c] = M.T;
+  }
+  return 0;
+}
+
+}  // extern "C"
