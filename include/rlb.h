@@ -385,6 +385,85 @@ rlb_status rlb_plane_check(rlb_plane* pl);
 rlb_status rlb_plane_flags(rlb_plane* pl, uint32_t* flags);
 const char* rlb_plane_last_error(const rlb_plane* pl);
 
+/*
+ * Multi-dimensional model on an (x, y, z) box: eq. Boltz_gen with the particle
+ * velocity v = (sin(theta) cos(phi), sin(theta) sin(phi), cos(theta)) resolved
+ * in all three directions, on the full product quadrature of the section
+ * "Discretization of the momentum space": q_p Gauss-Laguerre x q_xi
+ * Gauss-Legendre x every node phi_k = 2 pi k / q_phi (k = 0 .. q_phi - 1) of
+ * the trapezoid rule of eq. azimuthInt, weight 1/q_phi.  The flow may point
+ * anywhere: q_p * q_xi * q_phi points are evolved per cell.  The Landau frame
+ * is the timelike eigenvector of T^mu_nu (three velocity components); the
+ * truncated equilibrium (eq. feqtrunc) is the Legendre series of order n_v in
+ * c = v . u/|u| with the coefficients of the 1D projection at the speed |u|.
+ * Cells are cell-centred on [x_min, x_max] x [y_min, y_max] x [z_min, z_max];
+ * every face is an outflow (zero-gradient) boundary.  A box with ny = 1 and
+ * u^y = 0 evolves like a plane; one varying along z only with u along z like
+ * a tube.
+ *
+ *   nx, ny, nz -- cells, >= 1 each, nx * ny * nz <= 2^26 and, with rows
+ *                 padded to 64 cells, ceil(nx/64)*64 * ny * nz <= 2^27;
+ *   q_xi (<= 1024), q_phi, q_p, n_v, n_p -- as for a plane
+ *                 (n_v + 3 <= q_phi <= 64, any parity);
+ *   tau, T0, weno_eps -- as for a plane (the same weno_eps ranges);
+ *   dt         -- > 0: explicit; 0: min(cfl / (1/dx + 1/dy + 1/dz),
+ *                 dt_tau_max tau).  dt (1/dx + 1/dy + 1/dz) <= 1.5 and
+ *                 dt <= 2.5 tau are required.
+ *
+ * State layout (rlb_box_layout): F[s][z][y][ldx], s = (i q_xi + j) q_phi + k,
+ * precision of the box, ldx >= nx.  Ownership as for a plane: the caller owns
+ * the workspace (rlb_box_workspace_size bytes, 256-byte aligned) and the
+ * stream; calls are asynchronous on that stream except where noted.
+ */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t q_xi, q_phi, q_p;
+  int32_t n_v, n_p;
+  double x_min, x_max, y_min, y_max, z_min, z_max;
+  double tau;
+  double cfl;
+  double dt_tau_max;
+  double dt;
+  double T0;
+  double weno_eps;
+} rlb_box_desc;
+
+typedef struct rlb_box rlb_box;
+
+/* Defaults: 32^3 cells on [-0.5, 0.5]^3, q_xi 8, q_phi 8, q_p 3, n_v 5,
+ * n_p 2, tau 1e-2, cfl 0.5, dt_tau_max 0.5, T0 1, weno_eps 1e-6. */
+rlb_status rlb_box_defaults(rlb_box_desc* desc);
+/* Validates the descriptor and builds the host tables; no device work. */
+rlb_status rlb_box_create(const rlb_box_desc* desc, rlb_precision prec, rlb_box** out);
+rlb_status rlb_box_destroy(rlb_box* bx);
+rlb_status rlb_box_workspace_size(const rlb_box* bx, size_t* bytes);
+/* Binds the caller's device workspace and stream, clears it and uploads the
+ * tables (synchronizes). */
+rlb_status rlb_box_bind(rlb_box* bx, void* workspace, size_t bytes, void* hip_stream);
+/* Initial state: every cell takes the truncated equilibrium of its state
+ * fields_device[5][nz][ny][nx] (FP64 device memory: P, n, u^x, u^y, u^z;
+ * P, n > 0), which must stay valid until the stream reaches this call.  Time
+ * restarts at 0 and the sticky flag is cleared. */
+rlb_status rlb_box_set_initial_fields(rlb_box* bx, const double* fields_device);
+/* nsteps SSP-RK3 steps (three stage launches each). */
+rlb_status rlb_box_step(rlb_box* bx, int64_t nsteps);
+/* Fields [20][nz][ny][nx] (FP64 device memory): N0, Nx, Ny, Nz, T00, T0x,
+ * T0y, T0z, Txx, Txy, Txz, Tyy, Tyz, Tzz, e, n, v_x, v_y, v_z, T of the
+ * current state.  A non-physical cell sets the sticky flag. */
+rlb_status rlb_box_fields(rlb_box* bx, double* out_device);
+rlb_status rlb_box_layout(const rlb_box* bx, int64_t* state_elems, int64_t* ldx);
+/* Copy the current state out of / into the workspace (device buffers of
+ * state_elems elements); setting a state recomputes its records. */
+rlb_status rlb_box_get_state(rlb_box* bx, void* dst_device);
+rlb_status rlb_box_set_state(rlb_box* bx, const void* src_device);
+/* Time step, elapsed time and evolved points per cell (host values). */
+rlb_status rlb_box_info(const rlb_box* bx, double* dt, double* time, int32_t* Q);
+/* Synchronizes and reports the sticky non-physical flag. */
+rlb_status rlb_box_check(rlb_box* bx);
+/* Synchronizes and returns the sticky flag bits (RLB_FLAG_*). */
+rlb_status rlb_box_flags(rlb_box* bx, uint32_t* flags);
+const char* rlb_box_last_error(const rlb_box* bx);
+
 #ifdef __cplusplus
 }
 #endif

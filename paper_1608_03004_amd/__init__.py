@@ -3,4 +3,4 @@
 The product path is the HIP library ``librlb.so`` behind the C interface in
 ``include/rlb.h``; ``rlb`` is its Python binding.
 """
-from .rlb import Lattice, Plane, PlaneSpec, Tube, RLBError, load_library  # noqa: F401
+from .rlb import Box, BoxSpec, Lattice, Plane, PlaneSpec, Tube, RLBError, load_library  # noqa: F401

@@ -12,8 +12,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librlb.so")
-SOURCES = ["rlb_kernels.hip", "rlb_adjoint.hip", "rlb_feq.hip", "rlb_plane.hip", "rlb_noalloc.hip", "rlb_api.cpp", "rlb_plane_api.cpp",
-           "quadrature.cpp"]
+SOURCES = ["rlb_kernels.hip", "rlb_adjoint.hip", "rlb_feq.hip", "rlb_plane.hip", "rlb_box.hip", "rlb_noalloc.hip",
+           "rlb_api.cpp", "rlb_plane_api.cpp", "rlb_box_api.cpp", "quadrature.cpp"]
 ARCH = "gfx950"
 
 

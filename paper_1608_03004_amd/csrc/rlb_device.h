@@ -463,5 +463,43 @@ __device__ inline void weno5_grad(Real v1, Real v2, Real v3, Real v4, Real v5, R
   g[4] = w2 * Real(-1) * r6 + c2 * (b2t + b2s);
 }
 
+// Monomial coefficients of the Legendre polynomials, P_k(c) = sum_m L[k][m] c^m,
+// from the three-term recurrence (k+1) P_{k+1} = (2k+1) c P_k - k P_{k-1}.
+struct LegendreMonomials {
+  double c[kMaxNv + 1][kMaxNv + 1];
+};
+constexpr LegendreMonomials legendre_monomials() {
+  LegendreMonomials L{};
+  L.c[0][0] = 1.0;
+  L.c[1][1] = 1.0;
+  for (int k = 1; k < kMaxNv; ++k)
+    for (int m = 0; m <= k + 1; ++m)
+      L.c[k + 1][m] = ((2.0 * k + 1.0) * (m > 0 ? L.c[k][m - 1] : 0.0) - k * L.c[k - 1][m]) / (k + 1.0);
+  return L;
+}
+constexpr LegendreMonomials kLegendre = legendre_monomials();
+
+// The truncated series sum_k D[k] P_k(c) as a polynomial in c: coefficients
+// a[m] = sum_k D[k] L[k][m] (once per cell and radial node), then Horner's
+// rule per point.
+template <typename Real, int NVT>
+__device__ inline void series_monomials(const Real D[NVT + 1], Real a[NVT + 1]) {
+#pragma unroll
+  for (int m = 0; m <= NVT; ++m) {
+    Real acc = Real(0);
+#pragma unroll
+    for (int k = m; k <= NVT; ++k)
+      if (kLegendre.c[k][m] != 0.0) acc += D[k] * Real(kLegendre.c[k][m]);
+    a[m] = acc;
+  }
+}
+template <typename Real, int NVT>
+__device__ inline Real horner(const Real a[NVT + 1], Real c) {
+  Real f = a[NVT];
+#pragma unroll
+  for (int m = NVT - 1; m >= 0; --m) f = f * c + a[m];
+  return f;
+}
+
 }  // namespace dev
 }  // namespace rlb

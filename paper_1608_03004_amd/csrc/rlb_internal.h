@@ -243,6 +243,51 @@ hipError_t launch_plane_moments(int prec_fp32, const void* args, int grid, hipSt
 hipError_t launch_plane_fields(const PlaneDev* pl, int nx, int nz, const double* rec, double* out, unsigned* flag,
                                hipStream_t stream);
 
+// ---------------------------------------------------------------------------
+// Multi-dimensional model on an (x, y, z) box (rlb_box.hip, rlb_box_api.cpp)
+// ---------------------------------------------------------------------------
+// Point s = (i * qx + j) * qf + k: radial node i, polar node j, azimuthal node
+// k = 0 .. qf - 1 (every node of the trapezoid rule; nothing is mirrored).
+// State F[s][z][y][ldx], records rec[14][z][y][ldx] (N0, Nx, Ny, Nz, T00, T0x,
+// T0y, T0z, Txx, Txy, Txz, Tyy, Tyz, Tzz).  Velocity table row per (j, k):
+// v_x, v_y, v_z, then the weighted moment factors w {1, v_x, v_y, v_z, v_x^2,
+// v_x v_y, v_x v_z, v_y^2, v_y v_z, v_z^2} with w = w_xi[j] / qf.
+constexpr int kBoxVStride = 16;
+constexpr int kBoxTileX = 64, kBoxTileY = 4;  // cells per workgroup (one z layer)
+
+struct BoxDev {
+  int32_t nx, ny, nz, ldx;
+  int32_t qx, qf, qp, nv, np;
+  int32_t reserved;
+  int64_t slab;   // elements per z layer of one point (ny * ldx)
+  int64_t plane;  // elements per point (nz * slab)
+  double dx_inv, dy_inv, dz_inv, dt, tau_inv, T0, weno_eps;
+};
+
+template <typename Real>
+struct BoxArgs {
+  const BoxDev* bx;
+  int32_t stage;      // 1, 2, 3 (SSP-RK3 stage)
+  int32_t aux_pairs;
+  const Real* vtab;   // [qx * qf][kBoxVStride]
+  const double* itab; // radial rows (kIStride)
+  const Real* aux;    // projection rule (kAuxStride)
+  const Real* fin;
+  const Real* fn;
+  Real* fout;
+  const double* rec_in;
+  double* rec_out;
+  unsigned* flag;
+  const double* init;  // init kernel: per-cell P, n, u^x, u^y, u^z [5][nz][ny][nx]
+};
+
+int box_grid(int nx, int ny, int nz);
+hipError_t launch_box_stage(int prec_fp32, int qpt, int nvt, const void* args, int grid, hipStream_t stream);
+hipError_t launch_box_init(int prec_fp32, int qpt, int nvt, const void* args, int grid, hipStream_t stream);
+hipError_t launch_box_moments(int prec_fp32, const void* args, int grid, hipStream_t stream);
+hipError_t launch_box_fields(const BoxDev* bx, int64_t cells, const double* rec, double* out, unsigned* flag,
+                             hipStream_t stream);
+
 // Adjoint launchers (defined in rlb_adjoint.hip); one tube per call.
 hipError_t launch_adjoint_stage(int prec_fp32, int qpt, int nvt, int nx, int Q, const void* args, hipStream_t stream);
 hipError_t launch_tau_reduce(const TubeDev* tubes, int tube, const double* tau_acc, double* dL_dtau,

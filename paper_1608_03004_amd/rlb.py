@@ -70,6 +70,16 @@ class PlaneDesc(ctypes.Structure):
                 ("weno_eps", ctypes.c_double)]
 
 
+class BoxDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("q_xi", ctypes.c_int32), ("q_phi", ctypes.c_int32), ("q_p", ctypes.c_int32),
+                ("n_v", ctypes.c_int32), ("n_p", ctypes.c_int32),
+                ("x_min", ctypes.c_double), ("x_max", ctypes.c_double), ("y_min", ctypes.c_double),
+                ("y_max", ctypes.c_double), ("z_min", ctypes.c_double), ("z_max", ctypes.c_double),
+                ("tau", ctypes.c_double), ("cfl", ctypes.c_double), ("dt_tau_max", ctypes.c_double),
+                ("dt", ctypes.c_double), ("T0", ctypes.c_double), ("weno_eps", ctypes.c_double)]
+
+
 _SIGNATURES = {
     "rlb_tube_defaults": [ctypes.POINTER(TubeDesc)],
     "rlb_create": [ctypes.POINTER(TubeDesc), ctypes.c_int32, ctypes.c_int, ctypes.c_uint32, ctypes.POINTER(_VP)],
@@ -120,8 +130,23 @@ _SIGNATURES.update({
     "rlb_plane_info": [_VP, _DP, _DP, ctypes.POINTER(ctypes.c_int32)],
     "rlb_plane_check": [_VP],
     "rlb_plane_flags": [_VP, ctypes.POINTER(ctypes.c_uint32)],
+    "rlb_box_defaults": [ctypes.POINTER(BoxDesc)],
+    "rlb_box_create": [ctypes.POINTER(BoxDesc), ctypes.c_int, ctypes.POINTER(_VP)],
+    "rlb_box_destroy": [_VP],
+    "rlb_box_workspace_size": [_VP, ctypes.POINTER(ctypes.c_size_t)],
+    "rlb_box_bind": [_VP, _VP, ctypes.c_size_t, _VP],
+    "rlb_box_set_initial_fields": [_VP, _VP],
+    "rlb_box_step": [_VP, ctypes.c_int64],
+    "rlb_box_fields": [_VP, _VP],
+    "rlb_box_layout": [_VP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+    "rlb_box_get_state": [_VP, _VP],
+    "rlb_box_set_state": [_VP, _VP],
+    "rlb_box_info": [_VP, _DP, _DP, ctypes.POINTER(ctypes.c_int32)],
+    "rlb_box_check": [_VP],
+    "rlb_box_flags": [_VP, ctypes.POINTER(ctypes.c_uint32)],
 })
-_STRING_FUNCS = {"rlb_status_string": [ctypes.c_int], "rlb_last_error": [_VP], "rlb_plane_last_error": [_VP]}
+_STRING_FUNCS = {"rlb_status_string": [ctypes.c_int], "rlb_last_error": [_VP], "rlb_plane_last_error": [_VP],
+                 "rlb_box_last_error": [_VP]}
 
 
 def load_library():
@@ -577,4 +602,161 @@ class Plane:
     def flags(self) -> dict:
         f = ctypes.c_uint32()
         self._check(self.lib.rlb_plane_flags(self.h, ctypes.byref(f)))
+        return dict(nonphysical=bool(f.value & RLB_FLAG_NONPHYSICAL), fast_flow=bool(f.value & RLB_FLAG_FAST_FLOW))
+
+
+BOX_FIELDS = ("N0", "Nx", "Ny", "Nz", "T00", "T0x", "T0y", "T0z", "Txx", "Txy", "Txz", "Tyy", "Tyz", "Tzz",
+              "e", "n", "vx", "vy", "vz", "T")
+
+
+@dataclass
+class BoxSpec:
+    """An (x, y, z) box; fields mirror ``rlb_box_desc``."""
+    nx: int = 32
+    ny: int = 32
+    nz: int = 32
+    q_xi: int = 8
+    q_phi: int = 8
+    q_p: int = 3
+    n_v: int = 5
+    n_p: int = 2
+    tau: float = 1e-2
+    x_min: float = -0.5
+    x_max: float = 0.5
+    y_min: float = -0.5
+    y_max: float = 0.5
+    z_min: float = -0.5
+    z_max: float = 0.5
+    cfl: float = 0.5
+    dt_tau_max: float = 0.5
+    dt: float = 0.0
+    T0: float = 1.0
+    weno_eps: float = 1e-6
+
+    def c(self) -> BoxDesc:
+        return BoxDesc(self.nx, self.ny, self.nz, self.q_xi, self.q_phi, self.q_p, self.n_v, self.n_p, self.x_min,
+                       self.x_max, self.y_min, self.y_max, self.z_min, self.z_max, self.tau, self.cfl,
+                       self.dt_tau_max, self.dt, self.T0, self.weno_eps)
+
+    @property
+    def Q(self) -> int:
+        return self.q_p * self.q_xi * self.q_phi
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+class Box:
+    """The multi-dimensional model on an (x, y, z) box (workspace and stream
+    as for a Lattice)."""
+
+    def __init__(self, spec: BoxSpec, precision: str = "fp64", stream=None, device=None):
+        torch = _torch()
+        self.lib = load_library()
+        self.spec = spec
+        self.precision = precision
+        prec = {"fp64": RLB_FP64, "fp32": RLB_FP32}[precision]
+        self.dtype = torch.float64 if precision == "fp64" else torch.float32
+        h = _VP()
+        st = self.lib.rlb_box_create(ctypes.byref(spec.c()), prec, ctypes.byref(h))
+        if st != RLB_OK:
+            raise RLBError(st, self.lib.rlb_box_last_error(None).decode())
+        self.h = h
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        size = ctypes.c_size_t()
+        self._check(self.lib.rlb_box_workspace_size(self.h, ctypes.byref(size)))
+        self._ws = torch.empty(size.value + 256, dtype=torch.uint8, device=self.device)
+        self._ws_ptr = (self._ws.data_ptr() + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._check(self.lib.rlb_box_bind(self.h, _VP(self._ws_ptr), size.value, _VP(self.stream.cuda_stream)))
+        n, ld = ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.rlb_box_layout(self.h, ctypes.byref(n), ctypes.byref(ld)))
+        self.state_elems, self.ldx = n.value, ld.value
+
+    def _check(self, st: int):
+        if st != RLB_OK:
+            raise RLBError(st, self.lib.rlb_box_last_error(self.h).decode() or self.lib.rlb_status_string(st).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rlb_box_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.spec.nz, self.spec.ny, self.spec.nx)
+
+    def set_initial_fields(self, fields):
+        """fields: [5, nz, ny, nx] (P, n, u^x, u^y, u^z), numpy array or tensor."""
+        torch = _torch()
+        with torch.cuda.stream(self.stream):
+            f = torch.as_tensor(fields, dtype=torch.float64).to(self.device).contiguous()
+        assert tuple(f.shape) == (5,) + self.shape
+        self._check(self.lib.rlb_box_set_initial_fields(self.h, _VP(f.data_ptr())))
+        self.stream.synchronize()  # f may be freed after this call returns
+
+    def step(self, nsteps: int = 1):
+        self._check(self.lib.rlb_box_step(self.h, int(nsteps)))
+
+    def fields(self, out=None):
+        """Device tensor [20, nz, ny, nx] (FP64), queued on the stream."""
+        torch = _torch()
+        if out is None:
+            with torch.cuda.stream(self.stream):
+                out = torch.empty((20,) + self.shape, dtype=torch.float64, device=self.device)
+        self._check(self.lib.rlb_box_fields(self.h, _VP(out.data_ptr())))
+        return out
+
+    def moments(self) -> np.ndarray:
+        """Host copy [20, nz, ny, nx] of the fields; checks the sticky flag."""
+        f = self.fields()
+        self.stream.synchronize()
+        out = f.cpu().numpy()
+        self.check()
+        return out
+
+    def new_state(self):
+        torch = _torch()
+        return torch.empty(self.state_elems, dtype=self.dtype, device=self.device)
+
+    def get_state(self, out=None):
+        out = self.new_state() if out is None else out
+        self._check(self.lib.rlb_box_get_state(self.h, _VP(out.data_ptr())))
+        return out
+
+    def set_state(self, src):
+        assert src.numel() >= self.state_elems and src.dtype == self.dtype and src.is_contiguous()
+        self._check(self.lib.rlb_box_set_state(self.h, _VP(src.data_ptr())))
+
+    def state_array(self) -> np.ndarray:
+        """Host FP64 copy [Q, nz, ny, nx] of the current state (synchronizes)."""
+        s = self.get_state()
+        self.stream.synchronize()
+        return s.view((self.spec.Q,) + self.shape[:2] + (self.ldx,))[..., :self.spec.nx].double().cpu().numpy()
+
+    def load_array(self, F: np.ndarray):
+        """A state tensor holding the host array F[Q, nz, ny, nx]."""
+        torch = _torch()
+        s = torch.zeros((self.spec.Q,) + self.shape[:2] + (self.ldx,), dtype=self.dtype)
+        s[..., :self.spec.nx] = torch.as_tensor(F, dtype=self.dtype)
+        return s.reshape(-1).to(self.device)
+
+    def info(self):
+        dt, t, Q = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        self._check(self.lib.rlb_box_info(self.h, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(Q)))
+        return dict(dt=dt.value, time=t.value, Q=Q.value)
+
+    def check(self):
+        self._check(self.lib.rlb_box_check(self.h))
+
+    def flags(self) -> dict:
+        f = ctypes.c_uint32()
+        self._check(self.lib.rlb_box_flags(self.h, ctypes.byref(f)))
         return dict(nonphysical=bool(f.value & RLB_FLAG_NONPHYSICAL), fast_flow=bool(f.value & RLB_FLAG_FAST_FLOW))

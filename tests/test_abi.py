@@ -232,6 +232,56 @@ def test_valid_plane_create_and_host_queries(lib):
     assert lib.rlb_plane_destroy(h) == 0
 
 
+def _box_create(lib, spec, prec=rlb.RLB_FP64):
+    h = ctypes.c_void_p()
+    st = lib.rlb_box_create(ctypes.byref(spec.c()), prec, ctypes.byref(h))
+    return st, h
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(nx=0), rlb.RLB_ERR_INVALID_ARG),
+    (dict(ny=0), rlb.RLB_ERR_INVALID_ARG),
+    (dict(nx=1 << 9, ny=1 << 9, nz=1 << 9), rlb.RLB_ERR_INVALID_ARG),   # 2^27 cells
+    (dict(nx=8, ny=1 << 10, nz=1 << 12), rlb.RLB_ERR_INVALID_ARG),      # 2^25 cells, 2^28 padded
+    (dict(q_phi=7), rlb.RLB_ERR_INVALID_ARG),                           # q_phi < n_v + 3
+    (dict(q_phi=65), rlb.RLB_ERR_INVALID_ARG),
+    (dict(q_xi=1025), rlb.RLB_ERR_INVALID_ARG),
+    (dict(n_v=8), rlb.RLB_ERR_INVALID_ARG),
+    (dict(q_p=9), rlb.RLB_ERR_INVALID_ARG),
+    (dict(tau=0.0), rlb.RLB_ERR_INVALID_ARG),
+    (dict(y_min=0.5, y_max=-0.5), rlb.RLB_ERR_INVALID_ARG),
+    (dict(weno_eps=1e-12), rlb.RLB_ERR_INVALID_ARG),                    # below the product-form range
+    (dict(dt=0.02), rlb.RLB_ERR_UNSTABLE_DT),                           # dt (1/dx + 1/dy + 1/dz) = 1.92
+    (dict(dt=0.01, tau=0.003), rlb.RLB_ERR_UNSTABLE_DT),                # dt / tau = 3.3
+])
+def test_invalid_box_descriptors_are_rejected(lib, bad, status):
+    st, h = _box_create(lib, rlb.BoxSpec(**bad), rlb.RLB_FP32 if "weno_eps" in bad else rlb.RLB_FP64)
+    assert st == status and not h.value
+    assert lib.rlb_box_last_error(None)
+
+
+def test_valid_box_create_and_host_queries(lib):
+    d = rlb.BoxDesc()
+    assert lib.rlb_box_defaults(ctypes.byref(d)) == 0
+    assert (d.nx, d.ny, d.nz, d.q_xi, d.q_phi, d.q_p, d.n_v, d.n_p) == (32, 32, 32, 8, 8, 3, 5, 2)
+    spec = rlb.BoxSpec(nx=70, ny=6, nz=5, q_phi=9, tau=1.0)
+    st, h = _box_create(lib, spec)
+    assert st == 0, lib.rlb_box_last_error(None)
+    n, ld = ctypes.c_int64(), ctypes.c_int64()
+    assert lib.rlb_box_layout(h, ctypes.byref(n), ctypes.byref(ld)) == 0
+    assert ld.value == 128 and n.value == 3 * 8 * 9 * 5 * 6 * 128
+    size = ctypes.c_size_t()
+    assert lib.rlb_box_workspace_size(h, ctypes.byref(size)) == 0 and size.value >= 3 * n.value * 8
+    dt, t, Q = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+    assert lib.rlb_box_info(h, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(Q)) == 0
+    assert Q.value == 216 and abs(dt.value - 0.5 / (70 + 6 + 5)) < 1e-18
+    assert lib.rlb_box_step(h, 1) == rlb.RLB_ERR_STATE
+    assert lib.rlb_box_destroy(h) == 0
+    # a single cell is a valid box
+    st, h = _box_create(lib, rlb.BoxSpec(nx=1, ny=1, nz=1))
+    assert st == 0 and lib.rlb_box_destroy(h) == 0
+
+
 def test_missing_library_raises_instead_of_falling_back(monkeypatch, tmp_path):
     # the product path has no CPU or torch fallback: without librlb.so every
     # entry point raises
