@@ -72,9 +72,11 @@ def timed_steps(lat, steps):
     return wall, start.elapsed_time(stop) * 1e-3
 
 
-KERNEL_SOURCES = {"stage_kernel": "rlb_kernels.hip", "feq_kernel": "rlb_feq.hip", "plane_stage_kernel": "rlb_plane.hip"}
+KERNEL_SOURCES = {"stage_kernel": "rlb_kernels.hip", "feq_kernel": "rlb_feq.hip", "plane_stage_kernel": "rlb_plane.hip",
+                  "box_stage_kernel": "rlb_box.hip"}
 TRAFFIC_FILES = {"stage_kernel": "stage_kernel_traffic.json", "feq_kernel": "feq_kernel_traffic.json",
-                 "plane_stage_kernel": "plane_stage_kernel_traffic.json"}
+                 "plane_stage_kernel": "plane_stage_kernel_traffic.json",
+                 "box_stage_kernel": "box_stage_kernel_traffic.json"}
 
 
 def progress(msg):
@@ -559,6 +561,113 @@ def plane_error_table(a, b):
     return out
 
 
+def box_octants(nx, ny, nz):
+    """Per-cell (P, n, u^x, u^y, u^z) of a 3D Riemann problem on [-0.5, 0.5]^3:
+    eight constant states meeting at the centre, with flows along all three
+    axes (so every azimuthal node carries its own values)."""
+    import numpy as np
+    x = -0.5 + (np.arange(nx) + 0.5) / nx
+    y = -0.5 + (np.arange(ny) + 0.5) / ny
+    z = -0.5 + (np.arange(nz) + 0.5) / nz
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    f = np.zeros((5, nz, ny, nx))
+    for a in (0, 1):
+        for b in (0, 1):
+            for c in (0, 1):
+                m = ((X >= 0) == bool(a)) & ((Y >= 0) == bool(b)) & ((Z >= 0) == bool(c))
+                hi = (a + b + c) % 2 == 0
+                st = ((1.0 if hi else 0.2) * (1 + 0.2 * a), 1.0 if hi else 0.3, 0.1 * (a - b), 0.15 * (b - c),
+                      0.12 * (c - a))
+                for k in range(5):
+                    f[k][m] = st[k]
+    return f
+
+
+def box_step_bytes(spec, rsize):
+    """Algorithmic HBM bytes of one box step: 8 accesses per point (as for a
+    tube) and per cell and stage the 14 FP64 records read and written."""
+    return 8 * spec.cells * spec.Q * rsize + 3 * 224 * spec.cells
+
+
+def box_point_ops(spec):
+    """Algorithmic vector operations per point and stage of the box update:
+    three WENO5 faces of 37 operations each (one per direction: a face is
+    shared by the two cells beside it), the equilibrium polynomial in
+    c = v . u_hat (2 + N_v), advection and relaxation (11), the RK combination
+    (3) and the ten moment FMAs.  Per-cell work (Landau frame, projection) and
+    the faces a tile computes twice are excluded."""
+    return 3 * 37 + (2 + spec.n_v) + 11 + 3 + 10
+
+
+def leg_box(precision, steps, warmup=2, window_steps=2, window_half=4, n=128):
+    """The three-dimensional model: a 128^3 box, Q = 3 x 8 x 8 = 192 evolved
+    points (every azimuthal node), a 3D Riemann problem; a separate short run
+    gives a centre window the oracle can follow."""
+    import torch
+    from paper_1608_03004_amd import Box, BoxSpec
+    spec = BoxSpec(nx=n, ny=n, nz=n, q_xi=8, q_phi=8, q_p=3, tau=1e-2)
+    gb = Box(spec, precision=precision)
+    init = box_octants(n, n, n)
+    gb.set_initial_fields(init)
+    gb.step(warmup)
+    gb.check()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(gb.stream)
+    gb.step(steps)
+    stop.record(gb.stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gb.check()
+    fields = gb.moments()
+    ev = start.elapsed_time(stop) * 1e-3
+    rsize = 4 if precision == "fp32" else 8
+    launch_s = ev / (3 * steps)
+    bytes_launch = box_step_bytes(spec, rsize) / 3
+    pts = spec.cells * spec.Q
+    ops_launch = box_point_ops(spec) * pts
+    res = dict(value=pts * steps / wall, unit="cell*quad-point updates/s", ms_per_step=1e3 * wall / steps,
+               steps=steps,
+               roofline_alu=dict(bound="alu", achieved=round(ops_launch / launch_s / 1e9, 1), peak=VALU_PEAK_GOPS,
+                                 unit="Gop/s", frac=round(ops_launch / launch_s / 1e9 / VALU_PEAK_GOPS, 4),
+                                 kernel="box_stage_kernel", ops_per_point=box_point_ops(spec),
+                                 launch_us=round(launch_s * 1e6, 2)),
+               roofline_hbm=dict(bound="hbm", achieved=round(bytes_launch / launch_s / 1e9, 1), peak=HBM_PEAK_GBS,
+                                 unit="GB/s", frac=round(bytes_launch / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+                                 traffic=measured_traffic(f"box_octants/{precision}", "box_stage_kernel"),
+                                 kernel="box_stage_kernel", bytes_per_launch=int(bytes_launch)),
+               workload=f"box_octants: {n}^3 cells, Q = 3 x 8 x 8 = 192 (every azimuthal node), N_v = 5, "
+                        f"tau = 1e-2, 3D Riemann problem, {precision.upper()}")
+    gb.set_initial_fields(init)
+    gb.step(window_steps)
+    pad = 9 * window_steps
+    c = n // 2
+    short = gb.fields()[:, c - window_half:c + window_half, c - window_half:c + window_half,
+                        c - window_half:c + window_half].cpu().numpy()
+    a, b = c - window_half - pad, c + window_half + pad
+    lo, hi = -0.5 + a / n, -0.5 + b / n
+    win = dict(name=f"box_octants/{precision}", box=True,
+               spec=dict(nx=b - a, ny=b - a, nz=b - a, q_xi=8, q_phi=8, q_p=3, tau=1e-2, x_min=lo, x_max=hi,
+                         y_min=lo, y_max=hi, z_min=lo, z_max=hi, dt=gb.info()["dt"]),
+               init=init[:, a:b, a:b, a:b].copy(), nsteps=window_steps, pad=pad, half=window_half, gpu=short)
+    del gb
+    torch.cuda.empty_cache()
+    return res, fields, win
+
+
+def box_error_table(a, b):
+    """Max and L2 relative errors (normwise per field) of box fields."""
+    import numpy as np
+    names = dict(N0=0, T00=4, T0x=5, T0y=6, T0z=7, Txx=8, Txy=9, Tyy=11, Tzz=13, e=14, n=15, vx=16, vy=17, vz=18)
+    out = {}
+    for name, k in names.items():
+        d = a[k] - b[k]
+        s = max(np.abs(b[k]).max(), 1e-300)
+        out[name] = dict(max=float(np.abs(d).max() / s), l2=float(np.sqrt(np.mean(d * d)) / s))
+    return out
+
+
 def leg_copy(nbytes=1 << 30, reps=5):
     """Plain device-to-device copy through the library's copy kernel: the
     practical HBM ceiling, and the calibration of the HBM byte counters."""
@@ -659,7 +768,14 @@ def cpu_baseline(params, windows, target_s=12.0):
     errors, win_updates, win_secs = {}, 0, 0.0
     for w in windows:
         t0 = time.perf_counter()
-        if w.get("plane"):
+        if w.get("box"):
+            bx = O.Box(**w["spec"])
+            ref = O.box_fields(bx, O.box_run(bx, w["init"], w["nsteps"]))
+            p, h = w["pad"], w["half"]
+            ref = ref[:, p:p + 2 * h, p:p + 2 * h, p:p + 2 * h]
+            win_updates += bx.cells * bx.Q * w["nsteps"]
+            errors[w["name"]] = box_error_table(w["gpu"], ref)
+        elif w.get("plane"):
             pl = O.Plane(**w["spec"])
             Fp = O.plane_run(pl, w["init"], w["nsteps"])
             ref = O.plane_fields(pl, Fp)
@@ -697,10 +813,11 @@ def main():
     ap.add_argument("--tile", type=int, default=256)
     ap.add_argument("--precision", default="fp32", choices=("fp32", "fp64"),
                     help="form of the headline tube (fp64 is for profiling runs; the headline is fp32)")
-    ap.add_argument("--legs", default="fp64,tau,batched,adjoint,ballistic,high,plane,copy,stream,cpu",
-                    help="comma-separated extra legs (fp64, tau, batched, adjoint, ballistic, high, plane, copy, "
+    ap.add_argument("--legs", default="fp64,tau,batched,adjoint,ballistic,high,plane,box,copy,stream,cpu",
+                    help="comma-separated extra legs (fp64, tau, batched, adjoint, ballistic, high, plane, box, copy, "
                          "stream, cpu) or 'none'")
     ap.add_argument("--plane-steps", type=int, default=20)
+    ap.add_argument("--box-steps", type=int, default=10)
     ap.add_argument("--high-steps", type=int, default=20)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--ballistic-steps", type=int, default=20)
@@ -787,6 +904,13 @@ def main():
         line["plane"] = dict(fp32=p32, fp64=p64, fp32_vs_fp64_error=dict(
             after_steps=args.plane_steps + 2, fields=plane_error_table(pf32, pf64)))
         progress("plane done")
+    if "box" in legs:
+        b32, bf32, w32 = leg_box("fp32", args.box_steps)
+        b64, bf64, w64 = leg_box("fp64", args.box_steps)
+        windows += [w32, w64]
+        line["box"] = dict(fp32=b32, fp64=b64, fp32_vs_fp64_error=dict(
+            after_steps=args.box_steps + 2, fields=box_error_table(bf32, bf64)))
+        progress("box done")
     if "copy" in legs:
         line["copy"] = leg_copy()
     if "stream" in legs:
@@ -816,6 +940,8 @@ def main():
                 line.setdefault("high_order", {}).setdefault(form, {})["oracle_error"] = err
             elif leg == "plane_quadrants":
                 line.setdefault("plane", {}).setdefault(form, {})["oracle_error"] = err
+            elif leg == "box_octants":
+                line.setdefault("box", {}).setdefault(form, {})["oracle_error"] = err
         progress("cpu baseline done")
     print(json.dumps(line), flush=True)
 

@@ -183,8 +183,18 @@ __device__ inline Real reg_face(Real p0, Real p1, Real p2, Real p3, Real p4, Rea
   return up ? weno5(p0, p1, p2, p3, p4, eps4, unused) : weno5(p5, p4, p3, p2, p1, eps4, unused);
 }
 
+// Occupancy: four waves per SIMD for FP32 with Q_p <= 4 (the LDS of four
+// workgroups fills a CU; a few per-cell values spill outside the point loop;
+// measured 2.45 against 3.05 ms per stage on a 128^3 box with Q = 192 with
+// the compiler's three waves); the other forms are left to the compiler.
+template <typename Real, int QPT>
+constexpr int box_waves_per_eu() {
+  return (sizeof(Real) == 4 && QPT <= 4) ? 4 : 1;
+}
+
 template <typename Real, int QPT, int NVT, bool HAS_FN>
-__global__ __launch_bounds__(kBThreads) void box_stage_kernel(BoxArgs<Real> a) {
+__global__ __launch_bounds__(kBThreads) __attribute__((amdgpu_waves_per_eu(box_waves_per_eu<Real, QPT>())))
+void box_stage_kernel(BoxArgs<Real> a) {
   __shared__ Real lds[2 * kBBufElems];
   __shared__ double mom_lds[14][kBThreads];  // the 14 record sums of each lane
   const cptr<BoxDev> B = as_const(a.bx);

@@ -91,3 +91,30 @@ def test_error_table_fields():
     e = bench.error_table(a, b)
     assert abs(e["e"]["max"] - 1e-6) < 1e-12 and e["T00"]["max"] == 0 and e["u"]["max"] == 0
     assert set(e) == {"e", "u", "T00", "T0z", "Tzz", "N0", "n"}
+
+
+def test_box_models_and_oracle_window():
+    # 8 accesses per point, 14 FP64 records in and out per cell and stage;
+    # three WENO5 faces per point (one per direction)
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1608_03004_amd import BoxSpec
+    spec = BoxSpec(nx=128, ny=128, nz=128, q_xi=8, q_phi=8, q_p=3)
+    assert spec.Q == 192 and spec.cells == 1 << 21
+    assert bench.box_step_bytes(spec, 4) == 8 * (1 << 21) * 192 * 4 + 3 * 224 * (1 << 21)
+    assert bench.box_point_ops(spec) == 3 * 37 + 7 + 11 + 3 + 10 == 142
+    # the octant problem: eight states, flows along all three axes
+    f = bench.box_octants(6, 4, 2)
+    assert f.shape == (5, 2, 4, 6)
+    assert len({tuple(f[:, k, j, i]) for k in range(2) for j in range(4) for i in range(6)}) == 8
+    assert all(np.abs(f[c]).max() > 0 for c in (2, 3, 4))
+    # a window whose "GPU" result is the oracle's own run has no error
+    spec_w = dict(nx=10, ny=10, nz=10, q_xi=4, q_phi=8, q_p=3, tau=1e-2)
+    ob = O.Box(**spec_w)
+    init = bench.box_octants(10, 10, 10)
+    ref = O.box_fields(ob, O.box_run(ob, init, 1))
+    win = dict(name="box_octants/fp64", box=True, spec=spec_w, init=init, nsteps=1, pad=3, half=2,
+               gpu=ref[:, 3:7, 3:7, 3:7].copy())
+    _, errs = bench.cpu_baseline(dict(nx=1 << 20, q_xi=8, q_p=3, tau=1e-2), [win], target_s=0.05)
+    e = errs["box_octants/fp64"]
+    assert set(e) >= {"e", "n", "vx", "vy", "vz", "T00", "Txy"} and max(v["max"] for v in e.values()) == 0.0
