@@ -283,6 +283,8 @@ def leg_batched(steps, schedule=None):
                steps=steps, tubes=len(tubes), points_per_step=pts, schedule=lat.get_schedule(),
                roofline=roofline(tubes, 4, steps, ev, measured_traffic("sod_batched/fp32")),
                autotune_candidates=len(timings),
+               autotune_top=[dict(json.loads(k), ms_per_step=round(v * 1e3, 3))
+                             for k, v in sorted(timings.items(), key=lambda kv: kv[1])[:3]],
                workload="sod_batched: 4096 tubes, numpy default_rng(0): N_x~U{256..8192}, "
                         "Q_xi~U{8,16,32,64,128}, Q_p=3, log tau~U[ln1e-4,ln10], "
                         "log(P_L/P_R)~U[ln2,ln100], n_L/n_R~U[1,10], FP32")

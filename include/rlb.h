@@ -112,12 +112,21 @@ typedef struct {
   double P, n, u;
 } rlb_state;
 
-/* Launch schedule of the stage kernels (chosen by the autotuner). */
+/* Launch schedule of the stage kernels (chosen by the autotuner).  Every
+ * schedule gives bit-identical states and records.  Default after rlb_create:
+ * tile 256 (64 when 256-cell tiles would number fewer than half the CUs),
+ * no persistent grid, no graph replay, default chunk, split below the CU
+ * count. */
 typedef struct {
-  int32_t tile;        /* cells per workgroup: 128 or 256                       */
+  int32_t tile;        /* cells per workgroup: 64, 128 or 256                   */
   int32_t persistent;  /* 1: grid sized to the device, blocks loop over tiles   */
   int32_t blocks_per_cu; /* persistent grid = blocks_per_cu * CU count           */
   int32_t graph_steps; /* >0: replay time steps from a captured hipGraph of this many steps */
+  int32_t chunk;       /* quadrature points staged per LDS chunk: 0 (default: 8 in FP32, 4 in FP64)
+                          or twice the default                                  */
+  int32_t split_below; /* a kernel group with fewer work items than this spreads each stage over
+                          its radial nodes (one workgroup per tile and node, then a combine
+                          kernel); -1: the device's CU count (default), 0: never */
 } rlb_schedule;
 
 typedef struct rlb_lattice rlb_lattice;
@@ -256,6 +265,23 @@ rlb_status rlb_adjoint_step(rlb_lattice* lat, const void* state_n, void* lambda,
 rlb_status rlb_adjoint_segment_size(const rlb_lattice* lat, int32_t nsteps, size_t* bytes);
 rlb_status rlb_adjoint_segment(rlb_lattice* lat, const void* state0, int32_t nsteps, void* scratch, size_t bytes,
                                void* lambda, double* dL_dtau);
+/* The two halves of rlb_adjoint_segment, for callers that overlap the
+ * recomputation of one segment with the reverse sweep of the next one in
+ * reverse order (two scratch buffers, two streams; both halves are small,
+ * latency-bound launches that leave most of the GPU idle).
+ * rlb_adjoint_segment_forward recomputes the states of the nsteps steps from
+ * state0 into scratch on hip_stream (NULL: the lattice's stream);
+ * rlb_adjoint_segment_reverse applies the adjoint of those steps, last first,
+ * on the lattice's stream.  The caller orders them with events: a reverse
+ * sweep after the forward half that filled its scratch, and a forward half
+ * into a scratch after the reverse sweep that last read it.  The forward half
+ * uses none of the buffers of the reverse sweep, so the two may run at the
+ * same time; no rlb_step may run meanwhile.  Results equal rlb_adjoint_segment
+ * bit for bit. */
+rlb_status rlb_adjoint_segment_forward(rlb_lattice* lat, const void* state0, int32_t nsteps, void* scratch,
+                                       size_t bytes, void* hip_stream);
+rlb_status rlb_adjoint_segment_reverse(rlb_lattice* lat, int32_t nsteps, const void* scratch, size_t bytes,
+                                       void* lambda, double* dL_dtau);
 rlb_status rlb_fields_adjoint(rlb_lattice* lat, int32_t tube, const void* state, const double* dL_dfields, int64_t ld,
                               void* lambda);
 rlb_status rlb_initial_state_adjoint(rlb_lattice* lat, int32_t tube, const void* lambda0, double grad_left[3],

@@ -4,9 +4,11 @@ hand-written discrete adjoint.
 
 Memory is bounded by checkpointing: the forward keeps every c-th state
 (c = ceil(sqrt(nsteps)) by default); the backward walks the segments in
-reverse and hands each checkpoint to rlb_adjoint_segment, which recomputes
-the segment's states (with their stage states, kept in one scratch buffer of
-c steps) and applies the adjoint of every step in reverse order.  The time
+reverse: for each checkpoint rlb_adjoint_segment_forward recomputes the
+segment's states (with their stage states, in a scratch buffer of c steps)
+and rlb_adjoint_segment_reverse applies the adjoint of every step in reverse
+order; the recomputation of the next segment overlaps the reverse sweep of
+the current one (two buffers, two streams).  The time
 step is held fixed: the gradient with respect to tau is taken at constant dt.
 """
 import math
@@ -52,11 +54,37 @@ class SodProfile(torch.autograd.Function):
         lat.fields_adjoint(0, ctx.final, dfields, lam)
         dtau = torch.zeros(len(lat.tubes), dtype=torch.float64, device=lat.device)
         bounds = [k for k, _ in ctx.checkpoints] + [ctx.nsteps]
-        longest = max(k1 - k0 for (k0, _), k1 in zip(ctx.checkpoints, bounds[1:]))
-        scratch = torch.empty(lat.adjoint_segment_size(longest), dtype=torch.uint8, device=lat.device)
-        for seg in range(len(ctx.checkpoints) - 1, -1, -1):
-            k0, state = ctx.checkpoints[seg]
-            lat.adjoint_segment(state, bounds[seg + 1] - k0, scratch, lam, dtau)
+        segs = [(state, k1 - k0) for (k0, state), k1 in zip(ctx.checkpoints, bounds[1:])][::-1]  # reverse order
+        longest = max(n for _, n in segs)
+        # The forward recomputation of the next segment (in reverse order) runs
+        # on a side stream while the reverse sweep of the current one runs on
+        # the lattice's stream: both are chains of small launches that leave
+        # most of the GPU idle.  Two scratch buffers alternate; events order
+        # each buffer's fill before its sweep and its sweep before its next fill.
+        main = lat.stream
+        side = torch.cuda.Stream(device=lat.device)
+        side.wait_stream(main)
+        scratch = [torch.empty(lat.adjoint_segment_size(longest), dtype=torch.uint8, device=lat.device)
+                   for _ in range(2)]
+        filled = [torch.cuda.Event() for _ in range(2)]
+        freed = [torch.cuda.Event() for _ in range(2)]
+
+        def refill(r):
+            buf = r % 2
+            if r >= 2:
+                side.wait_event(freed[buf])
+            lat.adjoint_segment_forward(segs[r][0], segs[r][1], scratch[buf], side)
+            filled[buf].record(side)
+
+        refill(0)
+        for r, (_, n) in enumerate(segs):
+            if r + 1 < len(segs):
+                refill(r + 1)
+            main.wait_event(filled[r % 2])
+            lat.adjoint_segment_reverse(n, scratch[r % 2], lam, dtau)
+            freed[r % 2].record(main)
+        for s in scratch:
+            s.record_stream(side)
         gl, gr = lat.initial_state_adjoint(0, lam)
         dev, f64 = lat.device, torch.float64
         g = lambda v: torch.tensor(v, dtype=f64, device=dev)

@@ -2,7 +2,9 @@
 
 For a lattice it times a few time steps under each candidate schedule
 (cells per workgroup, plain or persistent grid with a number of resident
-workgroups per CU, hipGraph replay of several steps) and keeps the fastest.
+workgroups per CU, hipGraph replay of several steps, quadrature points per
+LDS chunk, the threshold below which a stage is spread over the radial nodes)
+and keeps the fastest.
 The lattice state and the tubes' clocks are saved before the sweep and
 restored afterwards.  Results
 are cached in a JSON file keyed by the device name, the precision and a
@@ -17,11 +19,24 @@ import time
 DEFAULT_CACHE = os.environ.get("RLB_AUTOTUNE_CACHE",
                                os.path.join(os.path.expanduser("~"), ".cache", "rlb_autotune.json"))
 
-CANDIDATES = (
-    [dict(tile=t, persistent=0, blocks_per_cu=4, graph_steps=g) for t in (128, 256) for g in (0, 8)]
-    + [dict(tile=t, persistent=1, blocks_per_cu=b, graph_steps=g)
-       for t in (128, 256) for b in (2, 4, 8) for g in (0, 8)]
-)
+def candidates_for(precision: str):
+    """The searched schedules: tile (64, 128, 256 cells), plain or persistent grid
+    (2, 4, 8 resident workgroups per CU), graph replay of 8 steps or none, the
+    default or doubled chunk of quadrature points, and the radial-node split
+    of small groups at its default threshold (the CU count), never, or always."""
+    ch2 = 16 if precision == "fp32" else 8
+    out = [dict(tile=t, persistent=0, blocks_per_cu=4, graph_steps=g, chunk=0, split_below=-1)
+           for t in (64, 128, 256) for g in (0, 8)]
+    out += [dict(tile=t, persistent=1, blocks_per_cu=b, graph_steps=g, chunk=0, split_below=-1)
+            for t in (64, 128, 256) for b in (2, 4, 8) for g in (0, 8)]
+    out += [dict(tile=t, persistent=0, blocks_per_cu=4, graph_steps=g, chunk=ch2, split_below=-1)
+            for t in (64, 128, 256) for g in (0, 8)]
+    out += [dict(tile=t, persistent=0, blocks_per_cu=4, graph_steps=8, chunk=0, split_below=s)
+            for t in (64, 128) for s in (0, 1 << 30)]
+    return out
+
+
+CANDIDATES = None  # per precision: candidates_for(lattice.precision)
 
 
 def signature(lat) -> str:
@@ -44,10 +59,12 @@ def _load(path):
         return {}
 
 
-def tune(lat, steps: int = 4, candidates=CANDIDATES, cache_path: str = DEFAULT_CACHE, use_cache: bool = True,
+def tune(lat, steps: int = 4, candidates=None, cache_path: str = DEFAULT_CACHE, use_cache: bool = True,
          verbose: bool = False):
     """Returns (best schedule dict, {schedule key: seconds per step}) and applies the best."""
     import torch
+    if candidates is None:
+        candidates = candidates_for(lat.precision)
     key = f"{_device_name()}|{signature(lat)}"
     cache = _load(cache_path) if use_cache else {}
     if use_cache and key in cache:

@@ -9,7 +9,8 @@
 //   (dL/dg)^T K = A^T K - rho K + B_s . mu(x),
 // with B_s the moment basis of point s and mu(x) = dR/dm^T K, obtained from a
 // reduction over the points of the cell followed by the adjoints of the
-// equilibrium projection and of the Landau matching.  Three kernels per stage:
+// equilibrium projection and of the Landau matching.  Three parts per stage
+// (the first two in one launch, adj_reduce_faces_kernel):
 //   adj_reduce   per cell (four waves share a cell's sums): mu(x), the rate
 //                constants and d/dtau,
 //   adj_faces    one lane per (point, face): WENO5 gradient times the face
@@ -38,26 +39,37 @@ using namespace dev;
 constexpr int kRedCells = 32, kRedGroups = 8;
 
 // acc[d][lane] = sum over groups (in group order) of part[d]; every group
-// reads the same combined values afterwards.  Ends with a barrier.
+// reads the same combined values afterwards.  Ends with a barrier.  The groups
+// post kSlotVals values at a time and group g sums value g of the batch over
+// the groups, so a batch costs two barriers whatever the group count.
+constexpr int kSlotVals = 8;
+static_assert(kSlotVals <= kRedGroups, "one summing group per posted value");
 template <int N>
 __device__ inline void combine_groups(double (*acc)[kRedCells], const double* part, int grp, int lane) {
-  for (int g = 0; g < kRedGroups; ++g) {
-    if (grp == g) {
+  __shared__ double slots[kRedGroups][kSlotVals][kRedCells];
 #pragma unroll
-      for (int d = 0; d < N; ++d) acc[d][lane] = (g == 0) ? part[d] : acc[d][lane] + part[d];
+  for (int d0 = 0; d0 < N; d0 += kSlotVals) {
+#pragma unroll
+    for (int dd = 0; dd < kSlotVals; ++dd)
+      if (d0 + dd < N) slots[grp][dd][lane] = part[d0 + dd];
+    __syncthreads();
+    if (grp < kSlotVals && d0 + grp < N) {
+      double s = slots[0][grp][lane];
+      for (int g = 1; g < kRedGroups; ++g) s += slots[g][grp][lane];
+      acc[d0 + grp][lane] = s;
     }
     __syncthreads();
   }
 }
 
 template <typename Real, int QPT, int NVT>
-__global__ __launch_bounds__(kRedCells * kRedGroups) void adj_reduce_kernel(AdjArgs<Real> a) {
+__device__ inline void adj_reduce_block(const AdjArgs<Real>& a, int block) {
   constexpr int ND = QPT * (NVT + 1);
   __shared__ double acc[ND + 3][kRedCells];
   const int lane = threadIdx.x % kRedCells, grp = threadIdx.x / kRedCells;
   const TubeDev& tb = a.tubes[a.tube];
   const int nx = tb.nx;
-  const int y = blockIdx.x * kRedCells + lane;
+  const int y = block * kRedCells + lane;
   const bool valid = y < nx;
   const int yc = valid ? y : nx - 1;
   const int64_t ldx = tb.ldx;
@@ -66,6 +78,26 @@ __global__ __launch_bounds__(kRedCells * kRedGroups) void adj_reduce_kernel(AdjA
   const cptr<double> itab = as_const(a.itab) + int64_t(tb.irow) * kIStride;
   double m[5];
   for (int c = 0; c < 5; ++c) m[c] = a.rec_g[tb.rec_off + c * ldx + yc];
+  // the first kPre points of each radial node that this group reduces below
+  // (j = grp + kRedGroups jj, jj < kPre): their loads go out before the Landau
+  // solve and the projection, which hide their latency.  One point per node:
+  // on the 4096-cell adjoint tube (Q = 32 x 3) FP32 gave 10.7e3 adjoint steps/s
+  // against 9.5e3 with four (the registers of four cost a wave per SIMD of
+  // the face blocks sharing the launch) and 10.0e3 with none.
+  constexpr int kPre = 1;
+  const Real* g = a.g + tb.f_off;
+  const Real* K = a.K + tb.f_off;
+  Real Kp[QPT][kPre], gp[QPT][kPre];
+#pragma unroll
+  for (int i = 0; i < QPT; ++i)
+#pragma unroll
+    for (int jj = 0; jj < kPre; ++jj) {
+      const int j = grp + kRedGroups * jj;
+      const bool has = i < qp && j < qx;
+      const int64_t row = has ? int64_t(i * qx + j) * ldx : 0;
+      Kp[i][jj] = has ? K[row + yc] : Real(0);
+      gp[i][jj] = has ? g[row + yc] : Real(0);
+    }
   const Macro M = landau(m);
 
   // 1. projection coefficients, bit for bit those of the forward stage kernel
@@ -93,8 +125,6 @@ __global__ __launch_bounds__(kRedCells * kRedGroups) void adj_reduce_kernel(AdjA
   // 2. reduction over the points (group grp takes j = grp, grp + G, ...)
   const double tau_inv = tb.tau_inv;
   const Real g0 = Real(M.gamma * tau_inv), g1 = Real(M.u * tau_inv);
-  const Real* g = a.g + tb.f_off;
-  const Real* K = a.K + tb.f_off;
   double red[ND + 3];
 #pragma unroll
   for (int d = 0; d < ND + 3; ++d) red[d] = 0.0;
@@ -104,16 +134,15 @@ __global__ __launch_bounds__(kRedCells * kRedGroups) void adj_reduce_kernel(AdjA
 #pragma unroll
   for (int i = 0; i < QPT; ++i) {
     if (i < qp) {
-#pragma unroll 4
-      for (int j = grp; j < qx; j += kRedGroups) {
+      // one point j of node i with its K and g values, in j order
+      auto point = [&](int j, Real Kr, Real gr) {
         const cptr<Real> J = jtab + j * kJStride;
         const Real xi = J[0];
-        const int64_t row = int64_t(i * qx + j) * ldx;
-        const double Kv = double(K[row + yc]);
+        const double Kv = double(Kr);
         Real e = Real(0);
 #pragma unroll
         for (int k = 0; k <= NVT; ++k) e += D[i][k] * J[4 + k];
-        const double diff = double(g[row + yc]) - double(e);
+        const double diff = double(gr) - double(e);
         const double rho = double(g0 - xi * g1);
         Gb -= Kv * diff * tau_inv;
         Ub += Kv * double(xi) * diff * tau_inv;
@@ -121,6 +150,14 @@ __global__ __launch_bounds__(kRedCells * kRedGroups) void adj_reduce_kernel(AdjA
 #pragma unroll
         for (int k = 0; k <= NVT; ++k) red[i * (NVT + 1) + k] += kr * double(J[4 + k]);
         taup += kr * tau_inv * diff;
+      };
+#pragma unroll
+      for (int jj = 0; jj < kPre; ++jj)
+        if (grp + kRedGroups * jj < qx) point(grp + kRedGroups * jj, Kp[i][jj], gp[i][jj]);
+#pragma unroll 4
+      for (int j = grp + kRedGroups * kPre; j < qx; j += kRedGroups) {
+        const int64_t row = int64_t(i * qx + j) * ldx;
+        point(j, K[row + yc], g[row + yc]);
       }
     }
   }
@@ -153,12 +190,11 @@ __global__ __launch_bounds__(kRedCells * kRedGroups) void adj_reduce_kernel(AdjA
 }
 
 template <typename Real>
-__global__ __launch_bounds__(256) void adj_faces_kernel(AdjArgs<Real> a) {
+__device__ inline void adj_faces_block(const AdjArgs<Real>& a, int bx, int s) {
   const TubeDev& tb = a.tubes[a.tube];
   const int nx = tb.nx;
-  const int fx = blockIdx.x * blockDim.x + threadIdx.x;  // face fx sits between cells fx-1 and fx
+  const int fx = bx * 256 + int(threadIdx.x);  // face fx sits between cells fx-1 and fx
   if (fx > nx) return;
-  const int s = blockIdx.y;
   const int j = s % tb.qx;
   const Real xi = a.jtab[int64_t(tb.jrow + j) * kJStride];
   const Real* g = a.g + tb.f_off + int64_t(s) * tb.ldx;
@@ -175,6 +211,22 @@ __global__ __launch_bounds__(256) void adj_faces_kernel(AdjArgs<Real> a) {
   Real* out = a.G + tb.face_off + int64_t(s) * tb.ldf + fx;
 #pragma unroll
   for (int m = 0; m < 5; ++m) out[m * a.G_slot] = phi * gr[m];
+}
+
+// The per-cell reduction and the face gradients read only the stage state and
+// the incoming adjoint, so one launch runs both: its first `nred` blocks are
+// reduction blocks, the rest face blocks (nfx per point).  The face blocks
+// fill the CUs the reduction leaves idle at the adjoint's sizes.
+static_assert(kRedCells * kRedGroups == 256, "reduction and face blocks share the block size");
+template <typename Real, int QPT, int NVT>
+__global__ __launch_bounds__(256) void adj_reduce_faces_kernel(AdjArgs<Real> a, int nred, int nfx) {
+  const int b = blockIdx.x;
+  if (b < nred) {
+    adj_reduce_block<Real, QPT, NVT>(a, b);
+  } else {
+    const int f = b - nred;
+    adj_faces_block<Real>(a, f % nfx, f / nfx);
+  }
 }
 
 template <typename Real>
@@ -338,9 +390,8 @@ __global__ void init_adjoint_final_kernel(const TubeDev* tubes, int tube, const 
 
 template <typename Real, int QPT, int NVT>
 hipError_t adjoint_stage_t(int nx, int Q, const AdjArgs<Real>& a, hipStream_t s) {
-  hipLaunchKernelGGL((adj_reduce_kernel<Real, QPT, NVT>), dim3((nx + kRedCells - 1) / kRedCells),
-                     dim3(kRedCells * kRedGroups), 0, s, a);
-  hipLaunchKernelGGL(adj_faces_kernel<Real>, dim3((nx + 1 + 255) / 256, Q), dim3(256), 0, s, a);
+  const int nred = (nx + kRedCells - 1) / kRedCells, nfx = (nx + 1 + 255) / 256;
+  hipLaunchKernelGGL((adj_reduce_faces_kernel<Real, QPT, NVT>), dim3(nred + nfx * Q), dim3(256), 0, s, a, nred, nfx);
   hipLaunchKernelGGL(adj_combine_kernel<Real>, dim3((nx + 255) / 256, Q), dim3(256), 0, s, a);
   return hipGetLastError();
 }

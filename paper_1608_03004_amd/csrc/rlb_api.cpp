@@ -75,7 +75,7 @@ struct rlb_lattice {
   bool initialised = false;
 
   // schedule and work lists
-  rlb_schedule sched = {256, 0, 4, 0};
+  rlb_schedule sched = {256, 0, 4, 0, 0, -1};
   std::vector<WorkItem> items;
   std::vector<Group> groups;
   int cu_count = 0;
@@ -263,12 +263,14 @@ rlb_status upload(rlb_lattice* L, size_t off, const void* src, size_t bytes) {
 LaunchShape shape(const rlb_lattice* L, const Group& g) {
   LaunchShape ls;
   ls.tile = L->sched.tile;
+  ls.chunk = L->sched.chunk > 0 ? L->sched.chunk : (L->prec == RLB_FP32 ? 8 : 4);
   const int n = g.item_end - g.item_begin;
   ls.grid = n;
   ls.nodes = 1;
+  const int split_below = L->sched.split_below < 0 ? L->cu_count : L->sched.split_below;
   if (L->sched.persistent) ls.grid = std::max(1, std::min(n, L->sched.blocks_per_cu * std::max(1, L->cu_count)));
   // too few tiles to fill the GPU: one workgroup per (tile, radial node)
-  else if (L->off_part && g.qp_max > 1 && n < L->cu_count) ls.nodes = g.qp_max;
+  else if (L->off_part && g.qp_max > 1 && n < split_below) ls.nodes = g.qp_max;
   return ls;
 }
 
@@ -571,7 +573,7 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
 
   // work-list bound: smallest tile
   int64_t max_items = 0;
-  for (auto& d : L->desc) max_items += (d.nx + 127) / 128;
+  for (auto& d : L->desc) max_items += (d.nx + 63) / 64;
   L->max_items = static_cast<int>(max_items);
 
   // workspace layout: first everything a time step uses besides the state
@@ -624,6 +626,11 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, dev) == hipSuccess) L->cu_count = prop.multiProcessorCount;
   }
+  // default tile: 256 cells, or 64 when 256-cell tiles would leave more than
+  // half of the CUs without work (small lattices: more, shorter workgroups)
+  int64_t tiles256 = 0;
+  for (auto& d : L->desc) tiles256 += (d.nx + 255) / 256;
+  if (L->cu_count > 0 && 2 * tiles256 < L->cu_count) L->sched.tile = 64;
   build_items(L);
   *out = L;
   return RLB_OK;
@@ -682,7 +689,12 @@ rlb_status rlb_set_stream(rlb_lattice* L, void* hip_stream) {
 
 rlb_status rlb_set_schedule(rlb_lattice* L, const rlb_schedule* s) {
   if (!L || !s) return RLB_ERR_INVALID_ARG;
-  if (s->tile != 128 && s->tile != 256) return fail(L, RLB_ERR_INVALID_ARG, "tile must be 128 or 256");
+  if (s->tile != 64 && s->tile != 128 && s->tile != 256)
+    return fail(L, RLB_ERR_INVALID_ARG, "tile must be 64, 128 or 256");
+  const int ch = L->prec == RLB_FP32 ? 8 : 4;
+  if (s->chunk != 0 && s->chunk != ch && s->chunk != 2 * ch)
+    return fail(L, RLB_ERR_INVALID_ARG, "chunk must be 0, the default (8 FP32, 4 FP64) or twice it");
+  if (s->split_below < -1) return fail(L, RLB_ERR_INVALID_ARG, "split_below must be >= -1");
   if (s->persistent != 0 && s->persistent != 1) return fail(L, RLB_ERR_INVALID_ARG, "persistent must be 0 or 1");
   if (s->blocks_per_cu < 1 || s->blocks_per_cu > 64) return fail(L, RLB_ERR_INVALID_ARG, "blocks_per_cu in [1, 64]");
   if (s->graph_steps < 0 || s->graph_steps > 4096) return fail(L, RLB_ERR_INVALID_ARG, "graph_steps in [0, 4096]");
@@ -973,25 +985,31 @@ rlb_status rlb_tables(const rlb_lattice* L, int32_t tube, double* xi, double* w_
 
 namespace {
 
-// One forward stage over every tube with explicit buffers (adjoint recompute).
+// One forward stage over every tube with explicit buffers (adjoint recompute),
+// on stream s (the lattice's stream by default).
 rlb_status run_stage(rlb_lattice* L, int stage, const void* fin, const void* fn, void* fout, const double* rec_in,
-                     double* rec_out) {
+                     double* rec_out, hipStream_t s) {
   const bool fp32 = L->prec == RLB_FP32;
   for (const Group& g : L->groups) {
-    const hipError_t e = fp32 ? stage_group<float>(L, g, stage, fin, fn, fout, rec_in, rec_out, L->stream)
-                              : stage_group<double>(L, g, stage, fin, fn, fout, rec_in, rec_out, L->stream);
+    const hipError_t e = fp32 ? stage_group<float>(L, g, stage, fin, fn, fout, rec_in, rec_out, s)
+                              : stage_group<double>(L, g, stage, fin, fn, fout, rec_in, rec_out, s);
     if (e != hipSuccess) return hip_fail(L, e, "stage kernel launch");
   }
   return RLB_OK;
 }
+rlb_status run_stage(rlb_lattice* L, int stage, const void* fin, const void* fn, void* fout, const double* rec_in,
+                     double* rec_out) {
+  return run_stage(L, stage, fin, fn, fout, rec_in, rec_out, L->stream);
+}
 
-rlb_status moments_of(rlb_lattice* L, const void* state, double* rec) {
+rlb_status moments_of(rlb_lattice* L, const void* state, double* rec, hipStream_t s) {
   hipError_t e = launch_moments(L->prec == RLB_FP32 ? 1 : 0, L->dev<TubeDev>(L->off_tubes),
                                 L->dev<WorkItem>(L->off_items), static_cast<int>(L->items.size()), L->sched.tile,
-                                L->ws + L->off_jtab, L->dev<double>(L->off_itab), state, rec, L->stream);
+                                L->ws + L->off_jtab, L->dev<double>(L->off_itab), state, rec, s);
   if (e != hipSuccess) return hip_fail(L, e, "moments kernel launch");
   return RLB_OK;
 }
+rlb_status moments_of(rlb_lattice* L, const void* state, double* rec) { return moments_of(L, state, rec, L->stream); }
 
 template <typename Real>
 rlb_status adjoint_stage(rlb_lattice* L, int tube, int qpt, int nvt, const void* g, const double* rec_g, const void* K,
@@ -1116,32 +1134,77 @@ rlb_status rlb_adjoint_segment_size(const rlb_lattice* L, int32_t nsteps, size_t
   return RLB_OK;
 }
 
-rlb_status rlb_adjoint_segment(rlb_lattice* L, const void* state0, int32_t nsteps, void* scratch, size_t bytes,
-                               void* lambda, double* dL_dtau) {
-  rlb_status st = need_adjoint(L);
-  if (st != RLB_OK) return st;
-  if (!state0 || !scratch || !lambda || !dL_dtau || nsteps < 1)
-    return fail(L, RLB_ERR_INVALID_ARG, "state0, scratch, lambda, dL_dtau and nsteps >= 1 are required");
+namespace {
+
+// Forward half of a segment: f^n, f1, f2 of every step and their records
+// into the scratch, on stream s.
+rlb_status segment_forward(rlb_lattice* L, const void* state0, int32_t nsteps, char* base, hipStream_t s) {
   const SegmentStep ss = segment_step(L);
-  if (bytes < ss.bytes * size_t(nsteps)) return fail(L, RLB_ERR_INVALID_ARG, "scratch smaller than rlb_adjoint_segment_size");
-  char* base = static_cast<char*>(scratch);
-  auto F = [&](int k, int s) { return static_cast<void*>(base + size_t(k) * ss.bytes + ss.F[s]); };
-  auto R = [&](int k, int s) { return reinterpret_cast<double*>(base + size_t(k) * ss.bytes + ss.R[s]); };
-  // forward: f^n, f1, f2 of every step of the segment and their records
-  hipError_t e = state_copy(F(0, 0), state0, L->state_elems * L->rsize, L->stream);
+  auto F = [&](int k, int i) { return static_cast<void*>(base + size_t(k) * ss.bytes + ss.F[i]); };
+  auto R = [&](int k, int i) { return reinterpret_cast<double*>(base + size_t(k) * ss.bytes + ss.R[i]); };
+  rlb_status st;
+  hipError_t e = state_copy(F(0, 0), state0, L->state_elems * L->rsize, s);
   if (e != hipSuccess) return hip_fail(L, e, "state copy");
-  if ((st = moments_of(L, F(0, 0), R(0, 0))) != RLB_OK) return st;
+  if ((st = moments_of(L, F(0, 0), R(0, 0), s)) != RLB_OK) return st;
   for (int k = 0; k < nsteps; ++k) {
-    if ((st = run_stage(L, 1, F(k, 0), F(k, 0), F(k, 1), R(k, 0), R(k, 1))) != RLB_OK) return st;
-    if ((st = run_stage(L, 2, F(k, 1), F(k, 0), F(k, 2), R(k, 1), R(k, 2))) != RLB_OK) return st;
-    if (k + 1 < nsteps && (st = run_stage(L, 3, F(k, 2), F(k, 0), F(k + 1, 0), R(k, 2), R(k + 1, 0))) != RLB_OK)
+    if ((st = run_stage(L, 1, F(k, 0), F(k, 0), F(k, 1), R(k, 0), R(k, 1), s)) != RLB_OK) return st;
+    if ((st = run_stage(L, 2, F(k, 1), F(k, 0), F(k, 2), R(k, 1), R(k, 2), s)) != RLB_OK) return st;
+    if (k + 1 < nsteps && (st = run_stage(L, 3, F(k, 2), F(k, 0), F(k + 1, 0), R(k, 2), R(k + 1, 0), s)) != RLB_OK)
       return st;
   }
-  // reverse
+  return RLB_OK;
+}
+
+// Reverse half: the adjoint of every step of the segment, last step first,
+// on the lattice's stream.
+rlb_status segment_reverse(rlb_lattice* L, int32_t nsteps, char* base, void* lambda, double* dL_dtau) {
+  const SegmentStep ss = segment_step(L);
+  auto F = [&](int k, int i) { return static_cast<void*>(base + size_t(k) * ss.bytes + ss.F[i]); };
+  auto R = [&](int k, int i) { return reinterpret_cast<double*>(base + size_t(k) * ss.bytes + ss.R[i]); };
+  rlb_status st;
   for (int k = nsteps - 1; k >= 0; --k)
     if ((st = adjoint_of_step(L, F(k, 0), F(k, 1), F(k, 2), R(k, 0), R(k, 1), R(k, 2), lambda, dL_dtau)) != RLB_OK)
       return st;
   return RLB_OK;
+}
+
+rlb_status segment_args(rlb_lattice* L, int32_t nsteps, const void* scratch, size_t bytes) {
+  if (!scratch || nsteps < 1) return fail(L, RLB_ERR_INVALID_ARG, "scratch and nsteps >= 1 are required");
+  if (bytes < segment_step(L).bytes * size_t(nsteps))
+    return fail(L, RLB_ERR_INVALID_ARG, "scratch smaller than rlb_adjoint_segment_size");
+  return RLB_OK;
+}
+
+}  // namespace
+
+rlb_status rlb_adjoint_segment(rlb_lattice* L, const void* state0, int32_t nsteps, void* scratch, size_t bytes,
+                               void* lambda, double* dL_dtau) {
+  rlb_status st = need_adjoint(L);
+  if (st != RLB_OK) return st;
+  if (!state0 || !lambda || !dL_dtau) return fail(L, RLB_ERR_INVALID_ARG, "state0, lambda and dL_dtau are required");
+  if ((st = segment_args(L, nsteps, scratch, bytes)) != RLB_OK) return st;
+  char* base = static_cast<char*>(scratch);
+  if ((st = segment_forward(L, state0, nsteps, base, L->stream)) != RLB_OK) return st;
+  return segment_reverse(L, nsteps, base, lambda, dL_dtau);
+}
+
+rlb_status rlb_adjoint_segment_forward(rlb_lattice* L, const void* state0, int32_t nsteps, void* scratch, size_t bytes,
+                                       void* hip_stream) {
+  rlb_status st = need_adjoint(L);
+  if (st != RLB_OK) return st;
+  if (!state0) return fail(L, RLB_ERR_INVALID_ARG, "state0 is required");
+  if ((st = segment_args(L, nsteps, scratch, bytes)) != RLB_OK) return st;
+  hipStream_t s = hip_stream ? static_cast<hipStream_t>(hip_stream) : L->stream;
+  return segment_forward(L, state0, nsteps, static_cast<char*>(scratch), s);
+}
+
+rlb_status rlb_adjoint_segment_reverse(rlb_lattice* L, int32_t nsteps, const void* scratch, size_t bytes,
+                                       void* lambda, double* dL_dtau) {
+  rlb_status st = need_adjoint(L);
+  if (st != RLB_OK) return st;
+  if (!lambda || !dL_dtau) return fail(L, RLB_ERR_INVALID_ARG, "lambda and dL_dtau are required");
+  if ((st = segment_args(L, nsteps, scratch, bytes)) != RLB_OK) return st;
+  return segment_reverse(L, nsteps, static_cast<char*>(const_cast<void*>(scratch)), lambda, dL_dtau);
 }
 
 rlb_status rlb_fields_adjoint(rlb_lattice* L, int32_t tube, const void* state, const double* dL_dfields, int64_t ld,

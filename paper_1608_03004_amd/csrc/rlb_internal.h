@@ -181,6 +181,7 @@ struct LaunchShape {
   int tile;
   int grid;
   int nodes;  // 1, or the group's radial-node bound for a split launch
+  int chunk;  // quadrature points per LDS chunk of the stage kernel
 };
 hipError_t launch_stage(int prec_fp32, int qpt, int nvt, const LaunchShape& ls, const void* args,
                         hipStream_t stream);

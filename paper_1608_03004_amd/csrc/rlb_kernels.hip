@@ -40,15 +40,18 @@ namespace {
 
 using namespace dev;
 
-// Points per chunk: 8 in FP32; 4 in FP64, where registers are scarcer.
+// Points per chunk by default: 8 in FP32; 4 in FP64, where registers are
+// scarcer.  A schedule may double it (fewer barriers per point).  The moment
+// sums always run in groups of chunk_points() points whatever the chunk of a
+// launch, so every schedule gives the same records.
 template <typename Real>
 constexpr int chunk_points() {
   return sizeof(Real) == 4 ? 8 : 4;
 }
 
 // Moment sums of one radial node's row of values, in the order the stage
-// kernel's epilogue uses (plain sums within chunks of chunk_points() points,
-// compensated across chunks), so that records computed from a stored state
+// kernel's epilogue uses (plain sums within groups of chunk_points() points,
+// compensated across groups), so that records computed from a stored state
 // are bitwise equal to the records written while the state was produced.
 template <typename Real, typename Get>
 __device__ inline void row_moments(const Real* jtab, int qx, Get get, double& s0, double& s1, double& s2) {
@@ -145,11 +148,16 @@ struct ChunkRows {
 };
 
 // Loads of one chunk: the tile's own cells for CH points and, in wave 0, the
-// 6-cell halo of all CH points with one instruction.
+// 6-cell halo of all CH points (one instruction per 64 halo values: lane l of
+// instruction q loads halo cell e % 6 of chunk point e / 6, e = l + 64 q).
+template <int CH>
+constexpr int halo_loads() {
+  return (6 * CH + 63) / 64;
+}
 template <typename Real, int CH>
 struct ChunkLoads {
   Real f[CH];
-  Real halo;
+  Real halo[halo_loads<CH>()];
 };
 
 template <typename Real, int TILE, int CH>
@@ -158,11 +166,22 @@ __device__ inline void issue_chunk(const Real* tube_f, int64_t ldx, uint32_t row
   const ChunkRows<Real, CH> rows(tube_f, ldx, row_bytes, qx, i, j0);
 #pragma unroll
   for (int c = 0; c < CH; ++c) L.f[c] = BufIO<Real>::template load<kLoadAux>(rows.r, vx, rows.soff(c, row_bytes));
-  if (t < 64) {  // wave 0: lane h + 6c loads halo cell h of chunk point c
-    const int c = min(t / 6, CH - 1), h = t % 6;
-    const int hx = h < 3 ? max(x0 - 3 + h, 0) : min(x0 + TILE + (h - 3), nx - 1);
-    const uint32_t off = uint32_t(min(c, rows.last)) * row_bytes + uint32_t(hx) * uint32_t(sizeof(Real));
-    L.halo = BufIO<Real>::template load<kLoadAux>(rows.r, off, 0);
+  if (t < 64) {
+    if constexpr (halo_loads<CH>() == 1) {  // lane h + 6c: halo cell h of chunk point c
+      const int c = min(t / 6, CH - 1), h = t % 6;
+      const int hx = h < 3 ? max(x0 - 3 + h, 0) : min(x0 + TILE + (h - 3), nx - 1);
+      const uint32_t off = uint32_t(min(c, rows.last)) * row_bytes + uint32_t(hx) * uint32_t(sizeof(Real));
+      L.halo[0] = BufIO<Real>::template load<kLoadAux>(rows.r, off, 0);
+    } else {
+#pragma unroll
+      for (int q = 0; q < halo_loads<CH>(); ++q) {
+        const int e = t + 64 * q;
+        const int c = min(e / 6, CH - 1), h = e % 6;
+        const int hx = h < 3 ? max(x0 - 3 + h, 0) : min(x0 + TILE + (h - 3), nx - 1);
+        const uint32_t off = uint32_t(min(c, rows.last)) * row_bytes + uint32_t(hx) * uint32_t(sizeof(Real));
+        L.halo[q] = BufIO<Real>::template load<kLoadAux>(rows.r, off, 0);
+      }
+    }
   }
 }
 
@@ -290,9 +309,20 @@ void stage_kernel(StageArgs<Real> a) {
         for (int e = 0; e < V; ++e) w[e] = cur.f[h * V + e];
         *reinterpret_cast<Vec*>(&tile[h][t + 3][0]) = w;
       }
-      if (t < 6 * CH) {
-        const int c = t / 6, h = t % 6;
-        tile[c / V][h < 3 ? h : TILE + h][c % V] = cur.halo;
+      if constexpr (halo_loads<CH>() == 1) {
+        if (t < 6 * CH) {
+          const int c = t / 6, h = t % 6;
+          tile[c / V][h < 3 ? h : TILE + h][c % V] = cur.halo[0];
+        }
+      } else if (t < 64) {
+#pragma unroll
+        for (int q = 0; q < halo_loads<CH>(); ++q) {
+          const int e = t + 64 * q;
+          if (e < 6 * CH) {
+            const int c = e / 6, h = e % 6;
+            tile[c / V][h < 3 ? h : TILE + h][c % V] = cur.halo[q];
+          }
+        }
       }
       __syncthreads();
       // WENO5 value at this lane's left face and, by CH
@@ -360,6 +390,8 @@ void stage_kernel(StageArgs<Real> a) {
       const int cj = min(CH, qx - j0);
       const ChunkRows<Real, CH> orow(fout, ldx, row_bytes, qx, i, j0);
       auto update = [&](auto full) {
+        constexpr int GP = chunk_points<Real>() / V;  // LDS planes per moment group
+        static_assert(NH % GP == 0, "a chunk is a whole number of moment groups");
         Real p0 = Real(0), p1 = Real(0), p2 = Real(0);
 #pragma unroll
         for (int h = 0; h < NH; ++h) {
@@ -397,13 +429,29 @@ void stage_kernel(StageArgs<Real> a) {
               p2 += J[3] * out;
             }
           }
+          if constexpr (NH > GP) {
+            if ((h + 1) % GP == 0) {
+              // one moment group of chunk_points() points, if it holds a
+              // point of the node
+              if (decltype(full)::value || (h + 1 - GP) * V < cj) {
+                acc.a0.add(p0);
+                acc.a1.add(p1);
+                acc.a2.add(p2);
+              }
+              p0 = Real(0);
+              p1 = Real(0);
+              p2 = Real(0);
+            }
+          }
           // keep the scheduler from hoisting the next plane's reads (bounds
           // the live registers; occupancy hides the latency instead)
           __builtin_amdgcn_sched_barrier(0);
         }
-        acc.a0.add(p0);
-        acc.a1.add(p1);
-        acc.a2.add(p2);
+        if constexpr (NH == GP) {  // the default chunk is one moment group
+          acc.a0.add(p0);
+          acc.a1.add(p1);
+          acc.a2.add(p2);
+        }
       };
       if (cj == CH)
         update(std::true_type{});
@@ -667,10 +715,9 @@ __global__ __launch_bounds__(256) void fill_u32_kernel(unsigned* p, int n, unsig
   if (k < n) p[k] = v;
 }
 
-template <typename Real, int TILE, int QPT, int NVT>
-hipError_t launch_stage_t(const LaunchShape& ls, const void* args, hipStream_t s) {
+template <typename Real, int TILE, int QPT, int NVT, int CH>
+hipError_t launch_stage_ch(const LaunchShape& ls, const void* args, hipStream_t s) {
   const StageArgs<Real>& a = *static_cast<const StageArgs<Real>*>(args);
-  constexpr int CH = chunk_points<Real>();
   const dim3 grid(ls.grid, ls.nodes);
   if (a.stage == 1)
     hipLaunchKernelGGL((stage_kernel<Real, TILE, QPT, NVT, false, CH>), grid, dim3(TILE), 0, s, a);
@@ -679,9 +726,18 @@ hipError_t launch_stage_t(const LaunchShape& ls, const void* args, hipStream_t s
   return hipGetLastError();
 }
 
+template <typename Real, int TILE, int QPT, int NVT>
+hipError_t launch_stage_t(const LaunchShape& ls, const void* args, hipStream_t s) {
+  constexpr int CH = chunk_points<Real>();
+  if (ls.chunk == CH) return launch_stage_ch<Real, TILE, QPT, NVT, CH>(ls, args, s);
+  if (ls.chunk == 2 * CH) return launch_stage_ch<Real, TILE, QPT, NVT, 2 * CH>(ls, args, s);
+  return hipErrorInvalidValue;
+}
+
 template <typename Real, int QPT, int NVT>
 hipError_t launch_stage_tile(const LaunchShape& ls, const void* args, hipStream_t s) {
   switch (ls.tile) {
+    case 64: return launch_stage_t<Real, 64, QPT, NVT>(ls, args, s);
     case 128: return launch_stage_t<Real, 128, QPT, NVT>(ls, args, s);
     case 256: return launch_stage_t<Real, 256, QPT, NVT>(ls, args, s);
     default: return hipErrorInvalidValue;
@@ -700,7 +756,9 @@ hipError_t launch_stage_real(int qpt, int nvt, const LaunchShape& ls, const void
 template <typename Real, int QPT, int NVT>
 hipError_t launch_init_t(const LaunchShape& ls, const void* args, hipStream_t s) {
   const InitArgs<Real>& a = *static_cast<const InitArgs<Real>*>(args);
-  if (ls.tile == 128) {
+  if (ls.tile == 64) {
+    hipLaunchKernelGGL((init_kernel<Real, 64, QPT, NVT>), dim3(ls.grid), dim3(64), 0, s, a);
+  } else if (ls.tile == 128) {
     hipLaunchKernelGGL((init_kernel<Real, 128, QPT, NVT>), dim3(ls.grid), dim3(128), 0, s, a);
   } else if (ls.tile == 256) {
     hipLaunchKernelGGL((init_kernel<Real, 256, QPT, NVT>), dim3(ls.grid), dim3(256), 0, s, a);

@@ -46,7 +46,8 @@ class State(ctypes.Structure):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("graph_steps", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("split_below", ctypes.c_int32)]
 
 
 class RLBError(RuntimeError):
@@ -109,6 +110,8 @@ _SIGNATURES = {
     "rlb_adjoint_step": [_VP, _VP, _VP, _VP],
     "rlb_adjoint_segment_size": [_VP, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)],
     "rlb_adjoint_segment": [_VP, _VP, ctypes.c_int32, _VP, ctypes.c_size_t, _VP, _VP],
+    "rlb_adjoint_segment_forward": [_VP, _VP, ctypes.c_int32, _VP, ctypes.c_size_t, _VP],
+    "rlb_adjoint_segment_reverse": [_VP, ctypes.c_int32, _VP, ctypes.c_size_t, _VP, _VP],
     "rlb_fields_adjoint": [_VP, ctypes.c_int32, _VP, _VP, ctypes.c_int64, _VP],
     "rlb_initial_state_adjoint": [_VP, ctypes.c_int32, _VP, _DP, _DP],
     "rlb_step_noalloc": [_VP, _VP, ctypes.c_int64, _VP, _VP],
@@ -260,14 +263,15 @@ class Lattice:
             pass
 
     # -- API -------------------------------------------------------------
-    def set_schedule(self, tile=256, persistent=0, blocks_per_cu=4, graph_steps=0):
-        s = Schedule(tile, persistent, blocks_per_cu, graph_steps)
+    def set_schedule(self, tile=256, persistent=0, blocks_per_cu=4, graph_steps=0, chunk=0, split_below=-1):
+        s = Schedule(tile, persistent, blocks_per_cu, graph_steps, chunk, split_below)
         self._check(self.lib.rlb_set_schedule(self.h, ctypes.byref(s)))
 
     def get_schedule(self) -> dict:
         s = Schedule()
         self._check(self.lib.rlb_get_schedule(self.h, ctypes.byref(s)))
-        return dict(tile=s.tile, persistent=s.persistent, blocks_per_cu=s.blocks_per_cu, graph_steps=s.graph_steps)
+        return dict(tile=s.tile, persistent=s.persistent, blocks_per_cu=s.blocks_per_cu, graph_steps=s.graph_steps,
+                    chunk=s.chunk, split_below=s.split_below)
 
     def set_initial_state(self, left, right, tube: int = -1):
         self._check(self.lib.rlb_set_initial_state(self.h, tube, State(*left), State(*right)))
@@ -415,6 +419,24 @@ def _lattice_adjoint_methods():
         self._check(self.lib.rlb_adjoint_segment(self.h, _VP(state0.data_ptr()), int(nsteps), _VP(scratch.data_ptr()),
                                                  scratch.numel(), _VP(lam.data_ptr()), _VP(dL_dtau.data_ptr())))
 
+    def adjoint_segment_forward(self, state0, nsteps: int, scratch, stream=None):
+        """Forward half of adjoint_segment: the segment's states into scratch, on
+        `stream` (a torch stream; default: the lattice's)."""
+        assert state0.dtype == self.dtype and state0.is_contiguous() and state0.numel() >= self.state_elems
+        assert scratch.is_contiguous() and scratch.element_size() == 1
+        s = _VP(stream.cuda_stream) if stream is not None else _VP(None)
+        self._check(self.lib.rlb_adjoint_segment_forward(self.h, _VP(state0.data_ptr()), int(nsteps),
+                                                         _VP(scratch.data_ptr()), scratch.numel(), s))
+
+    def adjoint_segment_reverse(self, nsteps: int, scratch, lam, dL_dtau):
+        """Reverse half of adjoint_segment on the lattice's stream."""
+        assert lam.dtype == self.dtype and lam.is_contiguous() and lam.numel() >= self.state_elems
+        assert scratch.is_contiguous() and scratch.element_size() == 1
+        assert dL_dtau.dtype.is_floating_point and dL_dtau.element_size() == 8 and dL_dtau.numel() >= len(self.tubes)
+        self._check(self.lib.rlb_adjoint_segment_reverse(self.h, int(nsteps), _VP(scratch.data_ptr()),
+                                                         scratch.numel(), _VP(lam.data_ptr()),
+                                                         _VP(dL_dtau.data_ptr())))
+
     def fields_adjoint(self, tube, state, dfields, lam):
         """Writes dL/df of a loss on the fields of `state` into tube's rows of lam."""
         assert dfields.element_size() == 8 and dfields.is_contiguous() and dfields.shape[0] == 10
@@ -430,6 +452,8 @@ def _lattice_adjoint_methods():
     Lattice.adjoint_step = adjoint_step
     Lattice.adjoint_segment_size = adjoint_segment_size
     Lattice.adjoint_segment = adjoint_segment
+    Lattice.adjoint_segment_forward = adjoint_segment_forward
+    Lattice.adjoint_segment_reverse = adjoint_segment_reverse
     Lattice.fields_adjoint = fields_adjoint
     Lattice.initial_state_adjoint = initial_state_adjoint
 

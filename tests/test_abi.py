@@ -82,10 +82,13 @@ def test_valid_create_and_host_queries(lib):
     # calls that need a bound workspace fail cleanly
     assert lib.rlb_step(h, 1) == rlb.RLB_ERR_STATE
     assert lib.rlb_set_initial_state(h, -1, rlb.State(1, 1, 0), rlb.State(0.1, 0.125, 0)) == rlb.RLB_ERR_STATE
-    s = rlb.Schedule(100, 0, 4, 0)
-    assert lib.rlb_set_schedule(h, ctypes.byref(s)) == rlb.RLB_ERR_INVALID_ARG
-    s = rlb.Schedule(128, 1, 4, 8)
-    assert lib.rlb_set_schedule(h, ctypes.byref(s)) == 0
+    for bad in (rlb.Schedule(100, 0, 4, 0, 0, -1), rlb.Schedule(128, 0, 4, 0, 16, -1),   # FP64 chunk 4 or 8
+                rlb.Schedule(128, 0, 4, 0, 0, -2), rlb.Schedule(128, 2, 4, 0, 0, -1)):
+        assert lib.rlb_set_schedule(h, ctypes.byref(bad)) == rlb.RLB_ERR_INVALID_ARG
+    for good in (rlb.Schedule(128, 1, 4, 8, 0, -1), rlb.Schedule(64, 0, 4, 0, 8, 0), rlb.Schedule(256, 0, 4, 0, 4, 64)):
+        assert lib.rlb_set_schedule(h, ctypes.byref(good)) == 0
+    got = rlb.Schedule()
+    assert lib.rlb_get_schedule(h, ctypes.byref(got)) == 0 and (got.tile, got.chunk, got.split_below) == (256, 4, 64)
     dt, t, Q = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
     assert lib.rlb_tube_info(h, 0, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(Q)) == 0
     assert abs(dt.value - 0.5 / 800) < 1e-18 and Q.value == 24

@@ -232,5 +232,17 @@ def test_adjoint_segment_equals_step_by_step_adjoint(torch_cuda, precision):
     lat.adjoint_segment(state0, nseg, scratch, lam_b, db)
     torch.cuda.synchronize()
     assert torch.equal(lam_a, lam_b) and torch.equal(da, db)
+    # the two halves, the forward on a side stream
+    lam_c, dc = lam0.clone(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    scratch2 = torch.empty_like(scratch)
+    side = torch.cuda.Stream()
+    side.wait_stream(lat.stream)
+    lat.adjoint_segment_forward(state0, nseg, scratch2, side)
+    ev = torch.cuda.Event()
+    ev.record(side)
+    lat.stream.wait_event(ev)
+    lat.adjoint_segment_reverse(nseg, scratch2, lam_c, dc)
+    torch.cuda.synchronize()
+    assert torch.equal(lam_a, lam_c) and torch.equal(da, dc)
     # the lattice's own state is untouched by the sweep
     assert torch.equal(lat.tube_view(lat.get_state()), lat.tube_view(states[-1]))

@@ -133,12 +133,19 @@ def test_fp64_batched_mixed_tubes(torch_cuda):
             assert normwise(lat.state_array(k), F).max() < 1e-12
 
 
-def test_schedules_and_graph_replays_are_bitwise_identical(torch_cuda):
-    params = [dict(nx=700, q_xi=8, q_p=3, tau=1e-2), dict(nx=333, q_xi=16, q_p=3, tau=1e-1)]
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_schedules_and_graph_replays_are_bitwise_identical(torch_cuda, precision):
+    # every schedule -- tile (64, 128, 256 cells), persistent grid, graph
+    # replay, doubled chunk, radial-node split forced on or off -- gives the
+    # same bits (odd q_xi: partial chunks and moment groups)
+    params = [dict(nx=700, q_xi=8, q_p=3, tau=1e-2), dict(nx=333, q_xi=19, q_p=3, tau=1e-1)]
+    ch2 = 16 if precision == "fp32" else 8
     results = []
     for sched in (dict(tile=256), dict(tile=256, persistent=1, blocks_per_cu=1),
-                  dict(tile=256, graph_steps=4), dict(tile=256, persistent=1, blocks_per_cu=2, graph_steps=3)):
-        lat = _lattice(params, schedule=sched)
+                  dict(tile=256, graph_steps=4), dict(tile=256, persistent=1, blocks_per_cu=2, graph_steps=3),
+                  dict(tile=64), dict(tile=64, chunk=ch2), dict(tile=128, chunk=ch2, graph_steps=4),
+                  dict(tile=64, split_below=0), dict(tile=256, chunk=ch2, split_below=1 << 20)):
+        lat = _lattice(params, precision=precision, schedule=sched)
         lat.set_initial_state(SOD_L, SOD_R)
         snaps = []
         for _ in range(3):  # several replays with eager work and syncs in between
@@ -159,7 +166,9 @@ def test_node_split_launch_matches_single_launch_bitwise(torch_cuda, precision):
     params = [dict(nx=300, q_xi=8, q_p=3, tau=1e-2), dict(nx=200, q_xi=12, q_p=2, n_p=1, tau=5e-2),
               dict(nx=150, q_xi=8, q_p=4, tau=1e-2)]
     runs = []
-    for sched in (dict(tile=128), dict(tile=128, persistent=1, blocks_per_cu=1)):
+    ch2 = 16 if precision == "fp32" else 8
+    for sched in (dict(tile=128), dict(tile=128, persistent=1, blocks_per_cu=1), dict(tile=64, chunk=ch2),
+                  dict(tile=64, split_below=0)):
         lat = _lattice(params, precision=precision, schedule=sched)
         lat.set_initial_state(SOD_L, SOD_R)
         lat.step(7)
@@ -168,8 +177,9 @@ def test_node_split_launch_matches_single_launch_bitwise(torch_cuda, precision):
         lat.set_state(lat.get_state().clone())
         for k in range(3):
             assert np.array_equal(lat.moments(k), runs[-1][3 + k])
-    for a, b in zip(*runs):
-        assert np.array_equal(a, b)
+    for other in runs[1:]:
+        for a, b in zip(runs[0], other):
+            assert np.array_equal(a, b)
     if precision == "fp64":
         from oracle import oracle as O
         for k, p in enumerate(params):
@@ -181,7 +191,7 @@ def test_zero_steps_and_single_tile_tubes(torch_cuda):
     # step(0) is a no-op; the smallest tubes (8 cells, one ragged tile) at both
     # tile sizes follow the oracle.
     params = [dict(nx=8, q_xi=4, q_p=3, tau=1e-2), dict(nx=9, q_xi=5, q_p=3, tau=1e-2)]
-    for tile in (128, 256):
+    for tile in (64, 128, 256):
         lat = _lattice(params, schedule=dict(tile=tile))
         lat.set_initial_state(SOD_L, SOD_R)
         before = [lat.state_array(k) for k in range(2)]
@@ -396,7 +406,8 @@ def test_high_order_batched_with_low_order_tubes_and_schedules(torch_cuda):
     lefts = [MOVING_L, (1.0, 1.0, 0.0), SOD_L, (2.0, 1.5, 0.2)]
     rights = [MOVING_R, (0.1, 0.125, 0.0), SOD_R, (0.1, 0.125, -0.1)]
     states = None
-    for sched in (dict(tile=256), dict(tile=128, persistent=1, blocks_per_cu=1), dict(tile=256, graph_steps=4)):
+    for sched in (dict(tile=256), dict(tile=128, persistent=1, blocks_per_cu=1), dict(tile=256, graph_steps=4),
+                  dict(tile=64, chunk=8), dict(tile=64, split_below=0)):
         lat = _lattice(plist, schedule=sched)
         lat.set_initial_states(lefts, rights)
         lat.step(12)
@@ -459,7 +470,11 @@ def test_autotuner_restores_state_and_keeps_results(torch_cuda, tmp_path):
     lat.step(3)
     clocks = [lat.info(k)["time"] for k in range(len(plist))]
     best, timings = autotune.tune(lat, steps=2, cache_path=str(tmp_path / "cache.json"))
-    assert best in [dict(c) for c in autotune.CANDIDATES] and len(timings) == len(autotune.CANDIDATES)
+    cands = autotune.candidates_for(lat.precision)
+    assert best in cands and len(timings) == len(cands)
+    assert {c["tile"] for c in cands} == {64, 128, 256} and {c["chunk"] for c in cands} == {0, 8}
+    assert {c["split_below"] for c in cands} == {-1, 0, 1 << 30}
+    assert lat.get_schedule() == best
     assert [lat.info(k)["time"] for k in range(len(plist))] == clocks  # the sweep's steps do not count
     lat.step(3)
     for k in (0, 17, 39):
