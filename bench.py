@@ -820,6 +820,9 @@ def main():
                          "stream, cpu) or 'none'")
     ap.add_argument("--plane-steps", type=int, default=20)
     ap.add_argument("--box-steps", type=int, default=10)
+    ap.add_argument("--adjoint-steps", type=int, default=2000,
+                    help="steps of the adjoint configuration (2000 is the benchmarked workload)")
+    ap.add_argument("--adjoint-fd", type=int, default=1, help="central-difference check of the FP64 gradients")
     ap.add_argument("--high-steps", type=int, default=20)
     ap.add_argument("--batched-steps", type=int, default=50)
     ap.add_argument("--ballistic-steps", type=int, default=20)
@@ -827,7 +830,8 @@ def main():
                     help="steps of the ballistic run checked against eq. ballistic (0: skip)")
     ap.add_argument("--tau-steps", type=int, default=2000)
     ap.add_argument("--batched-schedule", default="",
-                    help="tile,persistent,blocks_per_cu,graph_steps for the batched leg instead of autotuning")
+                    help="tile,persistent,blocks_per_cu,graph_steps[,chunk,split_below] for the batched leg "
+                         "instead of autotuning")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only (--gpus 1); the multi-GPU "
@@ -879,12 +883,13 @@ def main():
         bs = None
         if args.batched_schedule:
             v = [int(x) for x in args.batched_schedule.split(",")]
-            bs = dict(tile=v[0], persistent=v[1], blocks_per_cu=v[2], graph_steps=v[3])
+            bs = dict(zip(("tile", "persistent", "blocks_per_cu", "graph_steps", "chunk", "split_below"), v))
         line["batched"], wins = leg_batched(args.batched_steps, bs)
         windows += wins
         progress("batched done")
     if "adjoint" in legs:
-        line["adjoint"] = dict(fp64=leg_adjoint("fp64", fd=True), fp32=leg_adjoint("fp32"))
+        line["adjoint"] = dict(fp64=leg_adjoint("fp64", nsteps=args.adjoint_steps, fd=bool(args.adjoint_fd)),
+                               fp32=leg_adjoint("fp32", nsteps=args.adjoint_steps))
         g64, g32 = line["adjoint"]["fp64"], line["adjoint"]["fp32"]
         line["adjoint"]["fp32_vs_fp64_rel"] = dict(tau=abs(g32["grad_tau"] - g64["grad_tau"]) / abs(g64["grad_tau"]),
                                                    P_L=abs(g32["grad_P_L"] - g64["grad_P_L"]) / abs(g64["grad_P_L"]))
