@@ -402,13 +402,16 @@ def high_order_flops(tube):
     return 4 * ((tube.q_xi + 1) // 2) * B * tube.nx * tube.q_p
 
 
-def leg_high_order(precision, steps, warmup=2, reps=10):
-    """The large Sod tube with the high-order equilibrium (N_v = 63 = Q_xi - 1):
+def leg_high_order(precision, steps, warmup=2, reps=10, q_xi=64):
+    """The large Sod tube with the high-order equilibrium (N_v = Q_xi - 1):
     every stage runs the matrix-core pre-pass and then the stage kernel that
-    streams its output."""
+    streams its output.  Q_xi = 64 on 2^20 cells, or Q_xi = 128 on 2^19 cells
+    (the same number of points)."""
     import torch
     from paper_1608_03004_amd import Lattice, Tube
-    params = dict(nx=1 << 20, q_xi=64, q_p=4, n_v=63, tau=1e-2)
+    nx = (1 << 20) * 64 // q_xi
+    params = dict(nx=nx, q_xi=q_xi, q_p=4, n_v=q_xi - 1, tau=1e-2)
+    name = "sod_large_high_order" if q_xi == 64 else f"sod_large_high_order_q{q_xi}"
     tube = Tube(**params)
     lat = Lattice([tube], precision=precision)
     lat.set_initial_state(SOD_L, SOD_R)
@@ -417,7 +420,7 @@ def leg_high_order(precision, steps, warmup=2, reps=10):
     wall, ev = timed_steps(lat, steps)
     lat.check()
     fields = lat.moments(0)
-    win = window_request(f"sod_large_high_order/{precision}", params, SOD_L, SOD_R, steps + warmup,
+    win = window_request(f"{name}/{precision}", params, SOD_L, SOD_R, steps + warmup,
                          lat.info(0)["dt"], fields, half=64)
     # the pre-pass alone on the lattice's stream (same launch as inside a
     # stage), one launch per timing: inside a step each pre-pass alternates
@@ -444,12 +447,13 @@ def leg_high_order(precision, steps, warmup=2, reps=10):
                ms_per_step=1e3 * wall / steps, steps=steps,
                roofline=dict(bound="mfma", achieved=round(flops / feq_s / 1e12, 2), peak=MFMA_F64_PEAK_TFS,
                              unit="TFLOP/s", frac=round(flops / feq_s / 1e12 / MFMA_F64_PEAK_TFS, 4),
-                             traffic=measured_traffic(f"sod_large_high_order/{precision}", "feq_kernel"),
+                             traffic=measured_traffic(f"{name}/{precision}", "feq_kernel"),
                              kernel="feq_kernel", flops_per_launch=flops, launch_us=round(feq_s * 1e6, 2)),
                stage_roofline=dict(bound="hbm", achieved=round(stage_bytes / stage_s / 1e9, 1), peak=HBM_PEAK_GBS,
                                    unit="GB/s", frac=round(stage_bytes / stage_s / 1e9 / HBM_PEAK_GBS, 4),
                                    bytes_per_launch=int(stage_bytes), launch_us=round(stage_s * 1e6, 2)),
-               workload=f"sod_large_high_order: N_x=2^20, Q=64x4, N_v=63, N_p=2, tau=1e-2, {precision.upper()}")
+               workload=f"{name}: N_x=2^{nx.bit_length() - 1}, Q={q_xi}x4, N_v={q_xi - 1}, N_p=2, tau=1e-2, "
+                        f"{precision.upper()}")
     del lat, out
     torch.cuda.empty_cache()
     return res, fields, win
@@ -903,6 +907,10 @@ def main():
         windows += [w32, w64]
         line["high_order"] = dict(fp32=h32, fp64=h64, fp32_vs_fp64_error=dict(
             after_steps=args.high_steps + 2, fields=error_table(hf32, hf64)))
+        g32, _, wg32 = leg_high_order("fp32", args.high_steps, q_xi=128)
+        g64, _, wg64 = leg_high_order("fp64", args.high_steps, q_xi=128)
+        windows += [wg32, wg64]
+        line["high_order_q128"] = dict(fp32=g32, fp64=g64)
         progress("high-order done")
     if "plane" in legs:
         p32, pf32, w32 = leg_plane("fp32", args.plane_steps)
@@ -945,6 +953,8 @@ def main():
                 line.setdefault("ballistic", {})["oracle_error"] = err
             elif leg == "sod_large_high_order":
                 line.setdefault("high_order", {}).setdefault(form, {})["oracle_error"] = err
+            elif leg == "sod_large_high_order_q128":
+                line.setdefault("high_order_q128", {}).setdefault(form, {})["oracle_error"] = err
             elif leg == "plane_quadrants":
                 line.setdefault("plane", {}).setdefault(form, {})["oracle_error"] = err
             elif leg == "box_octants":

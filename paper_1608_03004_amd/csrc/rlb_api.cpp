@@ -27,6 +27,7 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 struct Group {
   int qpt, nvt;
   int qp_max;                // largest q_p of the group's tubes
+  int zj_max;                // largest high-order table rows of the group's tubes
   int item_begin, item_end;  // range in the item list
 };
 
@@ -185,11 +186,11 @@ rlb_status validate(const rlb_tube_desc& d, int k, std::string& msg) {
   if (d.nx < 8 || d.nx > (1 << 26)) return bad("nx must be in [8, 2^26]");
   if (d.q_xi < 1 || d.q_xi > 4096) return bad("q_xi must be in [1, 4096]");
   if (d.q_p < 1 || d.q_p > kMaxQp) return bad("q_p must be in [1, 8]");
-  if (d.n_v < 0 || d.n_v > kMaxNvHigh) return bad("n_v must be in [0, 63]");
-  // the high-order form (n_v > 7) keeps q_xi <= 64 and, as the quadrature
+  if (d.n_v < 0 || d.n_v > kMaxNvHigh) return bad("n_v must be in [0, 127]");
+  // the high-order form (n_v > 7) keeps q_xi <= 128 and, as the quadrature
   // section requires of the truncation, n_v < q_xi
   if (d.n_v > kMaxNv && (d.q_xi > kMaxQxHigh || d.n_v >= d.q_xi))
-    return bad("n_v > 7 needs n_v < q_xi <= 64");
+    return bad("n_v > 7 needs n_v < q_xi <= 128");
   if (d.n_p < 0 || d.n_p >= d.q_p) return bad("n_p must satisfy 0 <= n_p < q_p");
   if (d.n_p + 2 > 2 * d.q_p - 1) return bad("q_p too small to integrate T^{mu nu} of the equilibrium exactly");
   if (d.n_v + 2 > 2 * d.q_xi - 1) return bad("q_xi too small to integrate T^{mu nu} of the equilibrium exactly");
@@ -231,9 +232,11 @@ void build_items(rlb_lattice* L) {
     g.nvt = kv.first.second;
     g.item_begin = static_cast<int>(L->items.size());
     g.qp_max = 1;
+    g.zj_max = 0;
     std::vector<std::pair<int64_t, WorkItem>> tmp;
     for (int t : kv.second) {
       g.qp_max = std::max(g.qp_max, L->desc[t].q_p);
+      if (L->desc[t].n_v > kMaxNv) g.zj_max = std::max(g.zj_max, high_rows(L->desc[t].q_xi));
       const int64_t cost = int64_t(L->desc[t].q_xi) * L->desc[t].q_p;
       for (int x0 = 0; x0 < L->desc[t].nx; x0 += tile) tmp.push_back({cost, WorkItem{t, x0}});
     }
@@ -292,6 +295,7 @@ hipError_t equilibrium_pass(rlb_lattice* L, const Group& g, const double* rec, v
   f.sides = L->dev<double>(L->off_sides);
   f.tube_mask = L->dev<int32_t>(L->off_mask);
   f.out = static_cast<Real*>(out);
+  f.row_tiles = (g.zj_max + 15) / 16;
   LaunchShape ls;
   ls.tile = L->sched.tile;
   ls.grid = f.nitems;

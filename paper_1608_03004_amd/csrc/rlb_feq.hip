@@ -1,4 +1,4 @@
-// High-order equilibrium pre-pass (tubes with 7 < n_v <= 63, q_xi <= 64): the
+// High-order equilibrium pre-pass (tubes with 7 < n_v < q_xi <= 128): the
 // truncated expansion of the equilibrium (eq. feqtrunc, truncated at N_p and
 // N_v as the section on the equilibrium expansion describes) at every
 // quadrature point of every cell, for the stage kernel to read.
@@ -47,10 +47,19 @@ using namespace dev;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMaxS = high_aux_pairs(kMaxNvHigh) / 4;             // MFMA K-steps
-constexpr int kMaxZj = high_rows(kMaxQxHigh);                      // rows of Ze, Zo
-constexpr int kLdsLd = 4 * kMaxS + 1;                              // padded LDS row (doubles)
-static_assert(kMaxZj <= 32, "the kernel holds two row tiles of accumulators");
+// Two variants by the number RT of 16-row tiles of Ze, Zo: RT = 2 for
+// q_xi <= 64 (n_v <= 63, four waves per SIMD) and RT = 4 for q_xi <= 128
+// (n_v <= 127; the tables take 58.8 KB of LDS, so two waves per SIMD).
+template <int RT>
+struct FeqShape {
+  static constexpr int kMaxNv = RT == 2 ? 63 : kMaxNvHigh;
+  static constexpr int kMaxS = high_aux_pairs(kMaxNv) / 4;  // MFMA K-steps
+  static constexpr int kMaxZj = 16 * RT;                    // rows of Ze, Zo
+  static constexpr int kLdsLd = 4 * kMaxS + 1;              // padded LDS row (doubles)
+  static constexpr int kWaves = RT == 2 ? 4 : 2;
+};
+static_assert(FeqShape<4>::kMaxZj == high_rows(kMaxQxHigh), "the larger variant covers the polar order limit");
+static_assert(FeqShape<2>::kMaxNv + 1 == 64 && FeqShape<2>::kMaxZj == high_rows(64), "the smaller variant: q_xi <= 64");
 
 // 1/d for d > 0 (normal): hardware reciprocal refined by two Newton steps
 // (the error of each step is the square of the previous one's).
@@ -61,8 +70,10 @@ __device__ inline double recip(double d) {
   return r;
 }
 
-template <typename Real>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void feq_kernel(FeqArgs<Real> a) {
+template <typename Real, int RT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FeqShape<RT>::kWaves)))
+void feq_kernel(FeqArgs<Real> a) {
+  constexpr int kMaxS = FeqShape<RT>::kMaxS, kMaxZj = FeqShape<RT>::kMaxZj, kLdsLd = FeqShape<RT>::kLdsLd;
   __shared__ double zs[2 * kMaxZj * kLdsLd + 4 * kMaxS];  // Ze rows, Zo rows, x_b
   const int t = threadIdx.x, w = t / 64, l = t % 64, col = l % 16, quarter = l / 16;
   const cptr<WorkItem> items = as_const(a.items);
@@ -112,8 +123,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
       const double r = T / T0, pref = n / (4.0 * T * T0 * T0);
       for (int node = blockIdx.y; node < qp; node += gridDim.y) {
         const cptr<double> Lrow = itab + int64_t(irow + node) * kIStride + 4;  // L_l(p_node)
-        // two row tiles of Ze / Zo at most (q_xi <= 64): four accumulators
-        d4 ce0 = {0.0, 0.0, 0.0, 0.0}, co0 = ce0, ce1 = ce0, co1 = ce0;
+        // RT row tiles of Ze / Zo at most: 2 RT accumulators
+        d4 ce[RT], co[RT];
+#pragma unroll
+        for (int jt = 0; jt < RT; ++jt) {
+          ce[jt] = d4{0.0, 0.0, 0.0, 0.0};
+          co[jt] = ce[jt];
+        }
         const double* ae = zs + col * ld + quarter;
         const double* ao = ae + zj * ld;
         // the node's products for a compile-time radial order NP (the
@@ -138,11 +154,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
               }
               const double gp = yp * yp * sp, gm = ym * ym * sm;
               const double E = pref * (gp + gm), O = pref * (gp - gm);
-              ce0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ae[4 * s], E, ce0, 0, 0, 0);
-              co0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[4 * s], O, co0, 0, 0, 0);
-              if (njt > 1) {
-                ce1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ae[16 * ld + 4 * s], E, ce1, 0, 0, 0);
-                co1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[16 * ld + 4 * s], O, co1, 0, 0, 0);
+              ce[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ae[4 * s], E, ce[0], 0, 0, 0);
+              co[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[4 * s], O, co[0], 0, 0, 0);
+#pragma unroll
+              for (int jt = 1; jt < RT; ++jt) {
+                if (njt > jt) {
+                  ce[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ae[16 * jt * ld + 4 * s], E, ce[jt], 0, 0, 0);
+                  co[jt] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[16 * jt * ld + 4 * s], O, co[jt], 0, 0, 0);
+                }
               }
             }
           }
@@ -170,8 +189,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
               }
             }
           };
-          put(ce0, co0, 0);
-          if (njt > 1) put(ce1, co1, 1);
+          put(ce[0], co[0], 0);
+#pragma unroll
+          for (int jt = 1; jt < RT; ++jt)
+            if (njt > jt) put(ce[jt], co[jt], jt);
         }
       }
     }
@@ -182,10 +203,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
 
 hipError_t launch_feq(int prec_fp32, const LaunchShape& ls, const void* args, hipStream_t stream) {
   const dim3 grid(ls.grid, ls.nodes);
-  if (prec_fp32)
-    hipLaunchKernelGGL(feq_kernel<float>, grid, dim3(256), 0, stream, *static_cast<const FeqArgs<float>*>(args));
-  else
-    hipLaunchKernelGGL(feq_kernel<double>, grid, dim3(256), 0, stream, *static_cast<const FeqArgs<double>*>(args));
+  const int rt = prec_fp32 ? static_cast<const FeqArgs<float>*>(args)->row_tiles
+                           : static_cast<const FeqArgs<double>*>(args)->row_tiles;
+  if (rt < 1 || rt > 4) return hipErrorInvalidValue;
+  if (prec_fp32) {
+    const FeqArgs<float>& a = *static_cast<const FeqArgs<float>*>(args);
+    if (rt <= 2)
+      hipLaunchKernelGGL((feq_kernel<float, 2>), grid, dim3(256), 0, stream, a);
+    else
+      hipLaunchKernelGGL((feq_kernel<float, 4>), grid, dim3(256), 0, stream, a);
+  } else {
+    const FeqArgs<double>& a = *static_cast<const FeqArgs<double>*>(args);
+    if (rt <= 2)
+      hipLaunchKernelGGL((feq_kernel<double, 2>), grid, dim3(256), 0, stream, a);
+    else
+      hipLaunchKernelGGL((feq_kernel<double, 4>), grid, dim3(256), 0, stream, a);
+  }
   return hipGetLastError();
 }
 

@@ -375,6 +375,8 @@ HIGH_CASES = [
     dict(nx=200, q_xi=33, q_p=3, n_v=20, tau=5e-3),             # odd q_xi (xi = 0 node), zero table rows
     dict(nx=9, q_xi=9, q_p=3, n_v=8, tau=2e-2),                 # smallest high-order tube
     dict(nx=130, q_xi=16, q_p=8, n_v=15, n_p=3, tau=1e-1),      # q_p = 8 (n_p <= 3: radial series well conditioned)
+    dict(nx=200, q_xi=128, q_p=3, n_v=127, tau=1e-2),           # largest form: four row tiles of the tables
+    dict(nx=150, q_xi=100, q_p=3, n_v=80, tau=2e-2),            # between the two kernel variants
 ]
 MOVING_L, MOVING_R = (1.0, 1.0, 0.4), (0.3, 0.5, -0.6)
 
@@ -402,9 +404,9 @@ def test_high_order_batched_with_low_order_tubes_and_schedules(torch_cuda):
     # one lattice holding high- and low-order groups; every schedule (tile,
     # persistent grid, graph replay) gives the same bits and the oracle's values
     plist = [HIGH_CASES[1], dict(nx=300, q_xi=8, q_p=3, tau=1e-2), HIGH_CASES[0],
-             dict(nx=100, q_xi=32, q_p=3, n_v=31, tau=1e-2)]
-    lefts = [MOVING_L, (1.0, 1.0, 0.0), SOD_L, (2.0, 1.5, 0.2)]
-    rights = [MOVING_R, (0.1, 0.125, 0.0), SOD_R, (0.1, 0.125, -0.1)]
+             dict(nx=100, q_xi=32, q_p=3, n_v=31, tau=1e-2), HIGH_CASES[4]]
+    lefts = [MOVING_L, (1.0, 1.0, 0.0), SOD_L, (2.0, 1.5, 0.2), MOVING_L]
+    rights = [MOVING_R, (0.1, 0.125, 0.0), SOD_R, (0.1, 0.125, -0.1), MOVING_R]
     states = None
     for sched in (dict(tile=256), dict(tile=128, persistent=1, blocks_per_cu=1), dict(tile=256, graph_steps=4),
                   dict(tile=64, chunk=8), dict(tile=64, split_below=0)):

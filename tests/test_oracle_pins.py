@@ -95,7 +95,7 @@ def _perfect_fluid(n, T, u):
 
 
 @pytest.mark.parametrize("qx,qp,nv", [(4, 3, 5), (6, 3, 5), (8, 3, 5), (8, 4, 5), (64, 4, 5), (5, 3, 5),
-                                      (9, 3, 8), (33, 3, 20), (64, 4, 63)])
+                                      (9, 3, 8), (33, 3, 20), (64, 4, 63), (100, 3, 80), (128, 4, 127)])
 def test_equilibrium_moments_are_perfect_fluid(qx, qp, nv):
     # N^mu = n u^mu and T^{mu nu} = (e+P) u^mu u^nu + P g^{mu nu} with e = 3nT,
     # also for the high angular orders (N_v up to Q_xi - 1).
@@ -133,6 +133,13 @@ def test_rest_state_closed_form():
                     for pi in p])
     # (63 terms that vanish only up to rounding: a few ulps of the result)
     assert np.abs(F - ref[:, None]).max() < 3e-14 * ref.max()
+    # and at N_v = 127 (127 such terms)
+    high = O.Tube(nx=4, q_xi=128, q_p=3, n_v=127)
+    xi, wxi, p, wp = O.tables(high)
+    F = O.feq_nodes(high, 0.7, 1.7, 0.0).reshape(3, 128)
+    ref = np.array([0.7 / (4 * 1.7) * sum((1 - 1.7) ** l * sp.eval_genlaguerre(l, 1, pi) for l in range(3))
+                    for pi in p])
+    assert np.abs(F - ref[:, None]).max() < 4e-13 * ref.max()
 
 
 def _brute_coefficient(n, T, u, k, l):
@@ -222,12 +229,12 @@ def test_truncation_is_orthogonal_projection():
             assert abs(resid) < 1e-11
 
 
-@pytest.mark.parametrize("nv", [40, 63])
-def test_high_order_truncation_is_orthogonal_projection(nv):
+@pytest.mark.parametrize("qx,nv", [(64, 40), (64, 63), (128, 127)])
+def test_high_order_truncation_is_orthogonal_projection(qx, nv):
     # The defining property at high angular order: the residual F^eq - F_trunc
     # is orthogonal to every L_l(p) P_k(xi), k <= N_v, on an independent
     # 160 x 60 product rule.
-    tube = O.Tube(nx=4, q_xi=64, q_p=4, n_v=nv)
+    tube = O.Tube(nx=4, q_xi=qx, q_p=4, n_v=nv)
     n, T, v = 0.8, 1.2, 0.6
     u = v / math.sqrt(1 - v * v)
     g = math.sqrt(1 + u * u)
