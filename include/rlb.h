@@ -74,7 +74,7 @@ typedef enum { RLB_FP64 = 0, RLB_FP32 = 1 } rlb_precision;
  *                space"; Q_p = 3 suffices for N^mu and T^{mu nu}, section
  *                Riemann problem); q_p <= 8;
  *   n_v, n_p  -- truncation orders of eq. feqtrunc (the paper uses 5 and 2);
- *                n_p < q_p;  n_v <= 7, or 7 < n_v < q_xi <= 128 (the
+ *                n_p < q_p;  n_v <= 7, or 7 < n_v < q_xi <= 256 (the
  *                high-order form: the equilibrium is evaluated by a
  *                matrix-core pre-pass into one more state-sized buffer; no
  *                adjoint);  N^mu and T^{mu nu} of the equilibrium are exact

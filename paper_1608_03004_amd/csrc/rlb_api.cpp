@@ -186,11 +186,11 @@ rlb_status validate(const rlb_tube_desc& d, int k, std::string& msg) {
   if (d.nx < 8 || d.nx > (1 << 26)) return bad("nx must be in [8, 2^26]");
   if (d.q_xi < 1 || d.q_xi > 4096) return bad("q_xi must be in [1, 4096]");
   if (d.q_p < 1 || d.q_p > kMaxQp) return bad("q_p must be in [1, 8]");
-  if (d.n_v < 0 || d.n_v > kMaxNvHigh) return bad("n_v must be in [0, 127]");
-  // the high-order form (n_v > 7) keeps q_xi <= 128 and, as the quadrature
+  if (d.n_v < 0 || d.n_v > kMaxNvHigh) return bad("n_v must be in [0, 255]");
+  // the high-order form (n_v > 7) keeps q_xi <= 256 and, as the quadrature
   // section requires of the truncation, n_v < q_xi
   if (d.n_v > kMaxNv && (d.q_xi > kMaxQxHigh || d.n_v >= d.q_xi))
-    return bad("n_v > 7 needs n_v < q_xi <= 128");
+    return bad("n_v > 7 needs n_v < q_xi <= 256");
   if (d.n_p < 0 || d.n_p >= d.q_p) return bad("n_p must satisfy 0 <= n_p < q_p");
   if (d.n_p + 2 > 2 * d.q_p - 1) return bad("q_p too small to integrate T^{mu nu} of the equilibrium exactly");
   if (d.n_v + 2 > 2 * d.q_xi - 1) return bad("q_xi too small to integrate T^{mu nu} of the equilibrium exactly");

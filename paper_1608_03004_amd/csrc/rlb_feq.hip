@@ -1,4 +1,4 @@
-// High-order equilibrium pre-pass (tubes with 7 < n_v < q_xi <= 128): the
+// High-order equilibrium pre-pass (tubes with 7 < n_v < q_xi <= 256): the
 // truncated expansion of the equilibrium (eq. feqtrunc, truncated at N_p and
 // N_v as the section on the equilibrium expansion describes) at every
 // quadrature point of every cell, for the stage kernel to read.
@@ -47,19 +47,24 @@ using namespace dev;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Two variants by the number RT of 16-row tiles of Ze, Zo: RT = 2 for
-// q_xi <= 64 (n_v <= 63, four waves per SIMD) and RT = 4 for q_xi <= 128
-// (n_v <= 127; the tables take 58.8 KB of LDS, so two waves per SIMD).
-template <int RT>
+// Three variants by the number TT of 16-row tiles of Ze, Zo (the launch's
+// largest tube): TT = 2 for q_xi <= 64 (n_v <= 63, four waves per SIMD),
+// TT = 4 for q_xi <= 128 (n_v <= 127; 58.8 KB of tables in LDS, two waves per
+// SIMD) and TT = 8 for q_xi <= 256 (n_v <= 255): its tables (182 KB) exceed
+// the LDS, so the rows are split into blocks of RT = 4 tiles over the grid's
+// third dimension, each block staging its 64 rows (91.8 KB, one wave per
+// SIMD) and forming the B operands itself.
+template <int TT>
 struct FeqShape {
-  static constexpr int kMaxNv = RT == 2 ? 63 : kMaxNvHigh;
+  static constexpr int RT = TT < 4 ? TT : 4;                // row tiles per block
+  static constexpr int kMaxNv = TT == 2 ? 63 : (TT == 4 ? 127 : kMaxNvHigh);
   static constexpr int kMaxS = high_aux_pairs(kMaxNv) / 4;  // MFMA K-steps
-  static constexpr int kMaxZj = 16 * RT;                    // rows of Ze, Zo
+  static constexpr int kMaxZj = 16 * RT;                    // rows of Ze, Zo per block
   static constexpr int kLdsLd = 4 * kMaxS + 1;              // padded LDS row (doubles)
-  static constexpr int kWaves = RT == 2 ? 4 : 2;
+  static constexpr int kWaves = TT == 2 ? 4 : (TT == 4 ? 2 : 1);
 };
-static_assert(FeqShape<4>::kMaxZj == high_rows(kMaxQxHigh), "the larger variant covers the polar order limit");
-static_assert(FeqShape<2>::kMaxNv + 1 == 64 && FeqShape<2>::kMaxZj == high_rows(64), "the smaller variant: q_xi <= 64");
+static_assert(16 * 8 == high_rows(kMaxQxHigh), "the largest variant covers the polar order limit");
+static_assert(FeqShape<2>::kMaxNv + 1 == 64 && FeqShape<2>::kMaxZj == high_rows(64), "the smallest variant: q_xi <= 64");
 
 // 1/d for d > 0 (normal): hardware reciprocal refined by two Newton steps
 // (the error of each step is the square of the previous one's).
@@ -70,10 +75,12 @@ __device__ inline double recip(double d) {
   return r;
 }
 
-template <typename Real, int RT>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FeqShape<RT>::kWaves)))
+template <typename Real, int TT>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FeqShape<TT>::kWaves)))
 void feq_kernel(FeqArgs<Real> a) {
-  constexpr int kMaxS = FeqShape<RT>::kMaxS, kMaxZj = FeqShape<RT>::kMaxZj, kLdsLd = FeqShape<RT>::kLdsLd;
+  constexpr int RT = FeqShape<TT>::RT;
+  constexpr int kMaxS = FeqShape<TT>::kMaxS, kMaxZj = FeqShape<TT>::kMaxZj, kLdsLd = FeqShape<TT>::kLdsLd;
+  const int jt0 = RT * int(blockIdx.z);  // first row tile of this block
   __shared__ double zs[2 * kMaxZj * kLdsLd + 4 * kMaxS];  // Ze rows, Zo rows, x_b
   const int t = threadIdx.x, w = t / 64, l = t % 64, col = l % 16, quarter = l / 16;
   const cptr<WorkItem> items = as_const(a.items);
@@ -86,13 +93,20 @@ void feq_kernel(FeqArgs<Real> a) {
     const int qp = tb->qp, nx = tb->nx;
     if (int(blockIdx.y) >= qp) continue;
     const int zj = tb->zj, zb = tb->zb, ns = zb / 4, ld = zb + 1;
+    if (16 * jt0 >= zj) continue;  // the tube has no rows in this block
+    // this block's rows: Ze rows 16 jt0 .. 16 jt0 + zl - 1, then the same Zo rows
+    const int zl = min(kMaxZj, zj - 16 * jt0);
     __syncthreads();  // the previous item's reads of zs are done
     const double* zt = a.ztab + tb->z_off;
-    for (int e = t; e < 2 * zj * zb; e += blockDim.x) zs[(e / zb) * ld + e % zb] = zt[e];
-    double* xs = zs + 2 * zj * ld;
+    for (int e = t; e < 2 * zl * zb; e += blockDim.x) {
+      const int r = e / zb, b = e % zb;
+      const int src = r < zl ? 16 * jt0 + r : zj + 16 * jt0 + (r - zl);
+      zs[r * ld + b] = zt[src * zb + b];
+    }
+    double* xs = zs + 2 * zl * ld;
     for (int e = t; e < zb; e += blockDim.x) xs[e] = zt[2 * zj * zb + e];
     __syncthreads();
-    const int np = tb->np, qx = tb->qx, half = (qx + 1) / 2, njt = zj / 16, irow = tb->irow;
+    const int np = tb->np, qx = tb->qx, half = (qx + 1) / 2, njt = zl / 16, irow = tb->irow;
     const double T0 = tb->T0, z_min = tb->z_min, dz = tb->dz;
     const int64_t ldx = tb->ldx, rec_off = tb->rec_off;
     Real* out = a.out + tb->f_off;
@@ -131,7 +145,7 @@ void feq_kernel(FeqArgs<Real> a) {
           co[jt] = ce[jt];
         }
         const double* ae = zs + col * ld + quarter;
-        const double* ao = ae + zj * ld;
+        const double* ao = ae + zl * ld;
         // the node's products for a compile-time radial order NP (the
         // Laguerre values of the node held in registers)
         auto products = [&](auto np_c) {
@@ -181,7 +195,7 @@ void feq_kernel(FeqArgs<Real> a) {
           auto put = [&](const d4& ce, const d4& co, int jt) {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-              const int j = jt * 16 + 4 * rr + quarter;
+              const int j = (jt0 + jt) * 16 + 4 * rr + quarter;
               if (j < half) {
                 const int jm = qx - 1 - j;
                 orow[int64_t(j) * ldx] = Real(0.5 * (ce[rr] + co[rr]));
@@ -202,23 +216,24 @@ void feq_kernel(FeqArgs<Real> a) {
 }  // namespace
 
 hipError_t launch_feq(int prec_fp32, const LaunchShape& ls, const void* args, hipStream_t stream) {
-  const dim3 grid(ls.grid, ls.nodes);
   const int rt = prec_fp32 ? static_cast<const FeqArgs<float>*>(args)->row_tiles
                            : static_cast<const FeqArgs<double>*>(args)->row_tiles;
-  if (rt < 1 || rt > 4) return hipErrorInvalidValue;
-  if (prec_fp32) {
-    const FeqArgs<float>& a = *static_cast<const FeqArgs<float>*>(args);
+  if (rt < 1 || rt > 8) return hipErrorInvalidValue;
+  const dim3 grid(ls.grid, ls.nodes, rt <= 4 ? 1 : (rt + 3) / 4);
+  auto go = [&](auto real_tag) {
+    using Real = decltype(real_tag);
+    const FeqArgs<Real>& a = *static_cast<const FeqArgs<Real>*>(args);
     if (rt <= 2)
-      hipLaunchKernelGGL((feq_kernel<float, 2>), grid, dim3(256), 0, stream, a);
+      hipLaunchKernelGGL((feq_kernel<Real, 2>), grid, dim3(256), 0, stream, a);
+    else if (rt <= 4)
+      hipLaunchKernelGGL((feq_kernel<Real, 4>), grid, dim3(256), 0, stream, a);
     else
-      hipLaunchKernelGGL((feq_kernel<float, 4>), grid, dim3(256), 0, stream, a);
-  } else {
-    const FeqArgs<double>& a = *static_cast<const FeqArgs<double>*>(args);
-    if (rt <= 2)
-      hipLaunchKernelGGL((feq_kernel<double, 2>), grid, dim3(256), 0, stream, a);
-    else
-      hipLaunchKernelGGL((feq_kernel<double, 4>), grid, dim3(256), 0, stream, a);
-  }
+      hipLaunchKernelGGL((feq_kernel<Real, 8>), grid, dim3(256), 0, stream, a);
+  };
+  if (prec_fp32)
+    go(float(0));
+  else
+    go(double(0));
   return hipGetLastError();
 }
 

@@ -34,8 +34,8 @@ constexpr int kAuxPairsFP32 = 12;  // 24-point Gauss-Legendre rule
 // of j (xi_j' = -xi_j),
 //   F_j + F_j' = sum_b E_b Ze[j][b],  F_j - F_j' = sum_b O_b Zo[j][b],
 //   Ze[j][b] = Z(x_b, xi_j) + Z(x_b, -xi_j),  Zo[j][b] = Z(x_b, xi_j) - Z(x_b, -xi_j).
-constexpr int kMaxNvHigh = 127;       // angular truncation limit of that form
-constexpr int kMaxQxHigh = 128;       // polar order limit of that form
+constexpr int kMaxNvHigh = 255;       // angular truncation limit of that form
+constexpr int kMaxQxHigh = 256;       // polar order limit of that form
 constexpr int kNvtHigh = -1;          // kernel-group tag of that form
 // B: pairs of the auxiliary rule, a multiple of the MFMA's K = 4, with
 // 2 (2B) - n_v >= kHighExactMargin: the rule integrates P_k G for k <= n_v
@@ -158,7 +158,7 @@ struct FeqArgs {
   const double* sides;
   const int32_t* tube_mask;
   Real* out;
-  int32_t row_tiles;  // largest zj / 16 of the launch's tubes (kernel variant: 2 or 4)
+  int32_t row_tiles;  // largest zj / 16 of the launch's tubes (kernel variant: 2, 4 or 8)
 };
 
 template <typename Real>

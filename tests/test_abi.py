@@ -48,8 +48,8 @@ def test_defaults_are_the_papers(lib):
     (dict(q_p=2, n_p=1, n_v=5, q_xi=2), rlb.RLB_ERR_INVALID_ARG),   # q_xi too small for T^{mu nu}
     (dict(n_v=8), rlb.RLB_ERR_INVALID_ARG),                          # high-order form needs n_v < q_xi
     (dict(n_v=64, q_xi=64), rlb.RLB_ERR_INVALID_ARG),
-    (dict(n_v=128, q_xi=129), rlb.RLB_ERR_INVALID_ARG),             # n_v <= 127
-    (dict(n_v=20, q_xi=129), rlb.RLB_ERR_INVALID_ARG),              # ... and q_xi <= 128
+    (dict(n_v=256, q_xi=257), rlb.RLB_ERR_INVALID_ARG),             # n_v <= 255
+    (dict(n_v=20, q_xi=257), rlb.RLB_ERR_INVALID_ARG),              # ... and q_xi <= 256
     (dict(tau=0.0), rlb.RLB_ERR_INVALID_ARG),
     (dict(tau=-1.0), rlb.RLB_ERR_INVALID_ARG),
     (dict(T0=0.0), rlb.RLB_ERR_INVALID_ARG),
@@ -139,11 +139,11 @@ def test_plane_weno_epsilon_range(lib, eps, prec, ok):
 
 
 def test_high_order_tubes_create_without_adjoint(lib):
-    # 7 < n_v < q_xi <= 128: the matrix-core equilibrium form; it adds one
+    # 7 < n_v < q_xi <= 256: the matrix-core equilibrium form; it adds one
     # state-sized equilibrium buffer to the workspace and has no adjoint
     low = [rlb.Tube(nx=300, q_xi=64, q_p=4)]
     high = [rlb.Tube(nx=300, q_xi=64, q_p=4, n_v=63), rlb.Tube(nx=50, q_xi=9, q_p=2, n_v=8, n_p=1),
-            rlb.Tube(nx=70, q_xi=128, q_p=3, n_v=127)]
+            rlb.Tube(nx=70, q_xi=128, q_p=3, n_v=127), rlb.Tube(nx=20, q_xi=256, q_p=3, n_v=255)]
     st, h = _create(lib, low)
     assert st == 0
     base = ctypes.c_size_t()
@@ -156,12 +156,12 @@ def test_high_order_tubes_create_without_adjoint(lib):
     lib.rlb_workspace_size(h, ctypes.byref(size))
     assert size.value >= base.value + 256 * 320 * 8
     lib.rlb_destroy(h)
-    arr = (rlb.TubeDesc * 3)(*[t.c() for t in high])
+    arr = (rlb.TubeDesc * 4)(*[t.c() for t in high])
     h = ctypes.c_void_p()
-    assert lib.rlb_create(arr, 3, rlb.RLB_FP32, 0, ctypes.byref(h)) == 0
+    assert lib.rlb_create(arr, 4, rlb.RLB_FP32, 0, ctypes.byref(h)) == 0
     lib.rlb_destroy(h)
     h = ctypes.c_void_p()
-    assert lib.rlb_create(arr, 3, rlb.RLB_FP64, rlb.RLB_WITH_ADJOINT, ctypes.byref(h)) == rlb.RLB_ERR_INVALID_ARG
+    assert lib.rlb_create(arr, 4, rlb.RLB_FP64, rlb.RLB_WITH_ADJOINT, ctypes.byref(h)) == rlb.RLB_ERR_INVALID_ARG
     assert not h.value and b"n_v <= 7" in lib.rlb_last_error(None)
 
 

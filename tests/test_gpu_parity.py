@@ -376,7 +376,9 @@ HIGH_CASES = [
     dict(nx=9, q_xi=9, q_p=3, n_v=8, tau=2e-2),                 # smallest high-order tube
     dict(nx=130, q_xi=16, q_p=8, n_v=15, n_p=3, tau=1e-1),      # q_p = 8 (n_p <= 3: radial series well conditioned)
     dict(nx=200, q_xi=128, q_p=3, n_v=127, tau=1e-2),           # largest form: four row tiles of the tables
-    dict(nx=150, q_xi=100, q_p=3, n_v=80, tau=2e-2),            # between the two kernel variants
+    dict(nx=150, q_xi=100, q_p=3, n_v=80, tau=2e-2),            # between the variants of four and two row tiles
+    dict(nx=80, q_xi=256, q_p=3, n_v=255, tau=1e-2),            # largest form: two blocks of four row tiles
+    dict(nx=70, q_xi=170, q_p=3, n_v=130, tau=2e-2),            # second row block partly filled
 ]
 MOVING_L, MOVING_R = (1.0, 1.0, 0.4), (0.3, 0.5, -0.6)
 
@@ -404,9 +406,9 @@ def test_high_order_batched_with_low_order_tubes_and_schedules(torch_cuda):
     # one lattice holding high- and low-order groups; every schedule (tile,
     # persistent grid, graph replay) gives the same bits and the oracle's values
     plist = [HIGH_CASES[1], dict(nx=300, q_xi=8, q_p=3, tau=1e-2), HIGH_CASES[0],
-             dict(nx=100, q_xi=32, q_p=3, n_v=31, tau=1e-2), HIGH_CASES[4]]
-    lefts = [MOVING_L, (1.0, 1.0, 0.0), SOD_L, (2.0, 1.5, 0.2), MOVING_L]
-    rights = [MOVING_R, (0.1, 0.125, 0.0), SOD_R, (0.1, 0.125, -0.1), MOVING_R]
+             dict(nx=100, q_xi=32, q_p=3, n_v=31, tau=1e-2), HIGH_CASES[4], HIGH_CASES[6]]
+    lefts = [MOVING_L, (1.0, 1.0, 0.0), SOD_L, (2.0, 1.5, 0.2), MOVING_L, MOVING_L]
+    rights = [MOVING_R, (0.1, 0.125, 0.0), SOD_R, (0.1, 0.125, -0.1), MOVING_R, MOVING_R]
     states = None
     for sched in (dict(tile=256), dict(tile=128, persistent=1, blocks_per_cu=1), dict(tile=256, graph_steps=4),
                   dict(tile=64, chunk=8), dict(tile=64, split_below=0)):

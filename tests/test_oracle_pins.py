@@ -95,7 +95,8 @@ def _perfect_fluid(n, T, u):
 
 
 @pytest.mark.parametrize("qx,qp,nv", [(4, 3, 5), (6, 3, 5), (8, 3, 5), (8, 4, 5), (64, 4, 5), (5, 3, 5),
-                                      (9, 3, 8), (33, 3, 20), (64, 4, 63), (100, 3, 80), (128, 4, 127)])
+                                      (9, 3, 8), (33, 3, 20), (64, 4, 63), (100, 3, 80), (128, 4, 127),
+                                      (200, 3, 150), (256, 4, 255)])
 def test_equilibrium_moments_are_perfect_fluid(qx, qp, nv):
     # N^mu = n u^mu and T^{mu nu} = (e+P) u^mu u^nu + P g^{mu nu} with e = 3nT,
     # also for the high angular orders (N_v up to Q_xi - 1).
@@ -133,13 +134,14 @@ def test_rest_state_closed_form():
                     for pi in p])
     # (63 terms that vanish only up to rounding: a few ulps of the result)
     assert np.abs(F - ref[:, None]).max() < 3e-14 * ref.max()
-    # and at N_v = 127 (127 such terms)
-    high = O.Tube(nx=4, q_xi=128, q_p=3, n_v=127)
-    xi, wxi, p, wp = O.tables(high)
-    F = O.feq_nodes(high, 0.7, 1.7, 0.0).reshape(3, 128)
-    ref = np.array([0.7 / (4 * 1.7) * sum((1 - 1.7) ** l * sp.eval_genlaguerre(l, 1, pi) for l in range(3))
-                    for pi in p])
-    assert np.abs(F - ref[:, None]).max() < 4e-13 * ref.max()
+    # and at N_v = 127 and 255 (127 and 255 such terms)
+    for qx, tol in ((128, 4e-13), (256, 1e-12)):
+        high = O.Tube(nx=4, q_xi=qx, q_p=3, n_v=qx - 1)
+        xi, wxi, p, wp = O.tables(high)
+        F = O.feq_nodes(high, 0.7, 1.7, 0.0).reshape(3, qx)
+        ref = np.array([0.7 / (4 * 1.7) * sum((1 - 1.7) ** l * sp.eval_genlaguerre(l, 1, pi) for l in range(3))
+                        for pi in p])
+        assert np.abs(F - ref[:, None]).max() < tol * ref.max()
 
 
 def _brute_coefficient(n, T, u, k, l):
@@ -229,17 +231,18 @@ def test_truncation_is_orthogonal_projection():
             assert abs(resid) < 1e-11
 
 
-@pytest.mark.parametrize("qx,nv", [(64, 40), (64, 63), (128, 127)])
+@pytest.mark.parametrize("qx,nv", [(64, 40), (64, 63), (128, 127), (256, 255)])
 def test_high_order_truncation_is_orthogonal_projection(qx, nv):
     # The defining property at high angular order: the residual F^eq - F_trunc
     # is orthogonal to every L_l(p) P_k(xi), k <= N_v, on an independent
-    # 160 x 60 product rule.
+    # product rule of max(160, N_v + 70) x 60 points (exact for the products
+    # P_k P_k' of the truncation).
     tube = O.Tube(nx=4, q_xi=qx, q_p=4, n_v=nv)
     n, T, v = 0.8, 1.2, 0.6
     u = v / math.sqrt(1 - v * v)
     g = math.sqrt(1 + u * u)
     C = O.feq_coefficients(tube, n, T, u)
-    xa, wa = np.polynomial.legendre.leggauss(160)
+    xa, wa = np.polynomial.legendre.leggauss(max(160, nv + 70))
     pr, wr = sp.roots_genlaguerre(60, 1)
     Feq = n / (4 * T ** 3) * np.exp(pr[:, None] * (1 - (g - xa[None, :] * u) / T))
     Pk = np.array([sp.eval_legendre(k, xa) for k in range(nv + 1)])
