@@ -103,6 +103,7 @@ CASES = [
     (dict(nx=12, ny=10, nz=8, q_xi=6, q_phi=8, q_p=3, tau=math.inf), "blob"),   # collisionless
     (dict(nx=5, ny=1, nz=3, q_xi=4, q_phi=8, q_p=3, tau=1e-2), "octants"),      # degenerate extents
     (dict(nx=9, ny=13, nz=11, q_xi=5, q_phi=11, q_p=3, tau=2e-2), "blob"),      # odd everything
+    (dict(nx=6, ny=5, nz=4, q_xi=16, q_phi=64, q_p=8, n_p=3, n_v=7, tau=1e-2), "blob"),  # Q = 8 x 16 x 64
 ]
 
 
@@ -289,3 +290,59 @@ def test_box_full_size_windows(torch_cuda):
         errs = _fields_err_tensor_scale(full, ref)
         print(f"[box 128^3 fp32 {name} window] " + " ".join(f"{k}:{v:.1e}" for k, v in errs.items()), flush=True)
         assert max(errs.values()) < 1e-5, (name, errs)
+
+
+def test_box_max_size_windows(torch_cuda):
+    # the largest box the library accepts, 512 x 512 x 256 = 2^26 cells with
+    # Q = 192, FP32 (three states of 52 GB): a window at the centre and one at
+    # the upper corner (outflow faces, largest indices) follow the oracle on
+    # windows widened by 9 cells per step inward
+    from oracle import oracle as O
+    from paper_1608_03004_amd import Box, BoxSpec
+    nx, ny, nz, nsteps, w = 512, 512, 256, 2, 4
+    pad = 9 * nsteps
+    q = dict(q_xi=8, q_phi=8, q_p=3, tau=1e-2)
+    gb = Box(BoxSpec(nx=nx, ny=ny, nz=nz, **q), precision="fp32")
+    gb.set_initial_fields(_waves(O.Box(nx=nx, ny=ny, nz=nz, **q)))
+    gb.step(nsteps)
+    d = (1.0 / nx, 1.0 / ny, 1.0 / nz)
+    for name, c in (("centre", (nx // 2, ny // 2, nz // 2)), ("corner", (nx - w, ny - w, nz - w))):
+        a = [ci - w for ci in c]
+        b = [ci + w for ci in c]
+        lo = [ai - pad for ai in a]
+        hi = [min(bi + pad, n) for bi, n in zip(b, (nx, ny, nz))]
+        full = gb.fields()[:, a[2]:b[2], a[1]:b[1], a[0]:b[0]].cpu().numpy()
+        win = O.Box(nx=hi[0] - lo[0], ny=hi[1] - lo[1], nz=hi[2] - lo[2],
+                    x_min=-0.5 + lo[0] * d[0], x_max=-0.5 + hi[0] * d[0], y_min=-0.5 + lo[1] * d[1],
+                    y_max=-0.5 + hi[1] * d[1], z_min=-0.5 + lo[2] * d[2], z_max=-0.5 + hi[2] * d[2],
+                    dt=gb.info()["dt"], **q)
+        ref = O.box_fields(win, O.box_run(win, _waves(win), nsteps))
+        ref = ref[:, a[2] - lo[2]:b[2] - lo[2], a[1] - lo[1]:b[1] - lo[1], a[0] - lo[0]:b[0] - lo[0]]
+        errs = _fields_err_tensor_scale(full, ref)
+        print(f"[box 2^26 fp32 {name} window] " + " ".join(f"{k}:{v:.1e}" for k, v in errs.items()), flush=True)
+        assert max(errs.values()) < 1e-5, (name, errs)
+    del gb
+    torch_cuda.cuda.empty_cache()
+
+
+def test_box_full_size_fp64_window(torch_cuda):
+    # the benchmarked 128^3 box in FP64 on a centre window, to the FP64 bar
+    from oracle import oracle as O
+    from paper_1608_03004_amd import Box, BoxSpec
+    n, nsteps, w = 128, 2, 4
+    pad = 9 * nsteps
+    q = dict(q_xi=8, q_phi=8, q_p=3, tau=1e-2)
+    gb = Box(BoxSpec(nx=n, ny=n, nz=n, **q), precision="fp64")
+    gb.set_initial_fields(_octants(O.Box(nx=n, ny=n, nz=n, **q)))
+    gb.step(nsteps)
+    a, b = n // 2 - w, n // 2 + w
+    lo, hi = a - pad, b + pad
+    d = 1.0 / n
+    full = gb.fields()[:, a:b, a:b, a:b].cpu().numpy()
+    win = O.Box(nx=hi - lo, ny=hi - lo, nz=hi - lo, x_min=-0.5 + lo * d, x_max=-0.5 + hi * d,
+                y_min=-0.5 + lo * d, y_max=-0.5 + hi * d, z_min=-0.5 + lo * d, z_max=-0.5 + hi * d,
+                dt=gb.info()["dt"], **q)
+    ref = O.box_fields(win, O.box_run(win, _octants(win), nsteps))[:, a - lo:b - lo, a - lo:b - lo, a - lo:b - lo]
+    errs = _fields_err_tensor_scale(full, ref)
+    print("[box 128^3 fp64 centre window] " + " ".join(f"{k}:{v:.1e}" for k, v in errs.items()), flush=True)
+    assert max(errs.values()) < 1e-12, errs
