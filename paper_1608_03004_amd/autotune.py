@@ -74,8 +74,12 @@ def tune(lat, steps: int = 4, candidates=None, cache_path: str = DEFAULT_CACHE, 
     saved = lat.get_state().clone()
     clocks = [lat.info(t)["time"] for t in range(len(lat.tubes))]
     timings = {}
+    from .rlb import RLBError
     for cand in candidates:
-        lat.set_schedule(**cand)
+        try:
+            lat.set_schedule(**cand)
+        except RLBError:  # not valid for this lattice (e.g. a doubled chunk on the longest tubes)
+            continue
         lat.set_state(saved)
         g = cand["graph_steps"]
         n = max(steps, g) if g else steps

@@ -699,6 +699,10 @@ rlb_status rlb_set_schedule(rlb_lattice* L, const rlb_schedule* s) {
   if (s->chunk != 0 && s->chunk != ch && s->chunk != 2 * ch)
     return fail(L, RLB_ERR_INVALID_ARG, "chunk must be 0, the default (8 FP32, 4 FP64) or twice it");
   if (s->split_below < -1) return fail(L, RLB_ERR_INVALID_ARG, "split_below must be >= -1");
+  // a chunk's rows are one buffer resource of chunk * ldx * sizeof(Real) bytes (32-bit size)
+  const int64_t chunk_rows = s->chunk > 0 ? s->chunk : ch;
+  if (chunk_rows * int64_t(L->max_ldx) * int64_t(L->rsize) >= (int64_t(1) << 32))
+    return fail(L, RLB_ERR_INVALID_ARG, "chunk too large for the longest tube (chunk x padded row bytes >= 2^32)");
   if (s->persistent != 0 && s->persistent != 1) return fail(L, RLB_ERR_INVALID_ARG, "persistent must be 0 or 1");
   if (s->blocks_per_cu < 1 || s->blocks_per_cu > 64) return fail(L, RLB_ERR_INVALID_ARG, "blocks_per_cu in [1, 64]");
   if (s->graph_steps < 0 || s->graph_steps > 4096) return fail(L, RLB_ERR_INVALID_ARG, "graph_steps in [0, 4096]");

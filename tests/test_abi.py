@@ -90,6 +90,18 @@ def test_valid_create_and_host_queries(lib):
         assert lib.rlb_set_schedule(h, ctypes.byref(good)) == 0
     got = rlb.Schedule()
     assert lib.rlb_get_schedule(h, ctypes.byref(got)) == 0 and (got.tile, got.chunk, got.split_below) == (256, 4, 64)
+    lib.rlb_destroy(h)
+    # a doubled chunk of the longest tube (2^26 cells) would need a 2^32-byte buffer resource
+    for prec, ch in ((rlb.RLB_FP32, 16), (rlb.RLB_FP64, 8)):
+        st, h = _create(lib, [rlb.Tube(nx=1 << 26)], prec=prec)
+        assert st == 0
+        assert lib.rlb_set_schedule(h, ctypes.byref(rlb.Schedule(256, 0, 4, 0, ch, -1))) == rlb.RLB_ERR_INVALID_ARG
+        assert lib.rlb_set_schedule(h, ctypes.byref(rlb.Schedule(256, 0, 4, 0, 0, -1))) == 0
+        lib.rlb_destroy(h)
+        st, h = _create(lib, [rlb.Tube(nx=(1 << 26) - 64)], prec=prec)
+        assert lib.rlb_set_schedule(h, ctypes.byref(rlb.Schedule(256, 0, 4, 0, ch, -1))) == 0
+        lib.rlb_destroy(h)
+    st, h = _create(lib, tubes)
     dt, t, Q = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
     assert lib.rlb_tube_info(h, 0, ctypes.byref(dt), ctypes.byref(t), ctypes.byref(Q)) == 0
     assert abs(dt.value - 0.5 / 800) < 1e-18 and Q.value == 24
