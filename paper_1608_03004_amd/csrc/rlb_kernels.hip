@@ -193,10 +193,10 @@ struct Moments3 {
 };
 
 // Waves per SIMD the register allocation must allow.  The first stage of a
-// step (no f^n stream) is limited by its arithmetic, and one more resident
-// wave per SIMD there outweighs the few registers it spills (measured on the
-// Q_p <= 4 groups: +1 % FP32, +2 % FP64 per step); stages 2 and 3 of those
-// groups are bandwidth-bound and keep every value in registers.  The FP32
+// step (no f^n stream) of the Q_p <= 4 groups runs at 4 waves with every value
+// in registers (5 waves with a few spilled registers measured 2 % slower in
+// FP32); stages 2 and 3 of those groups are bandwidth-bound and keep every
+// value in registers at the compiler's choice (4 waves in FP32).  The FP32
 // Q_p <= 8 group runs at 4 waves instead of the compiler's 3 (a 2^19-cell tube
 // with Q = 64 x 5: 1.35 against 1.41 ms per step); its FP64 form keeps all
 // its coefficients in registers (3 waves measured 18 % slower).  The
@@ -205,7 +205,7 @@ struct Moments3 {
 template <typename Real, int QPT, int NVT, bool HAS_FN>
 constexpr int stage_waves_per_simd() {
   return NVT < 0 ? 1
-                 : QPT > 4 ? (sizeof(Real) == 4 ? 4 : 1) : (HAS_FN ? 1 : (sizeof(Real) == 4 ? 5 : 4));
+                 : QPT > 4 ? (sizeof(Real) == 4 ? 4 : 1) : (HAS_FN ? 1 : 4);
 }
 
 template <typename Real, int TILE, int QPT, int NVT, bool HAS_FN, int CH>
@@ -329,12 +329,12 @@ void stage_kernel(StageArgs<Real> a) {
       // WENO5 value at this lane's left face and, by CH
       // lanes, at the tile's right-most face.  The six values at tile
       // positions t..t+5 cover both upwind directions; the direction is a
-      // branch on the chunk's sign pattern, a wave-uniform bit mask from
-      // scalar table reads (all points of a chunk share the sign of xi except
-      // in the chunk that straddles xi = 0).
-      uint32_t pos_mask = 0;
-#pragma unroll
-      for (int c = 0; c < CH; ++c) pos_mask |= uint32_t(jtab[min(j0 + c, qx - 1) * kJStride] >= Real(0)) << c;
+      // branch on the chunk's sign pattern, a wave-uniform bit mask: the polar
+      // nodes are sorted and exactly symmetric (the middle node of an odd rule
+      // is exactly 0), so xi_j >= 0 exactly for j >= q_xi / 2, and all points
+      // of a chunk share the sign of xi except in the chunk that straddles 0.
+      const int jpos = min(max(qx / 2 - j0, 0), CH);  // first chunk point with xi >= 0
+      const uint32_t pos_mask = jpos >= 32 ? 0u : (~0u << jpos);
       Real own[CH];
       bool ok = true;  // every face of this lane had a usable product-form denominator
 #pragma unroll
@@ -470,7 +470,11 @@ void stage_kernel(StageArgs<Real> a) {
         else
           update(std::false_type{}, std::false_type{});
       }
-      __syncthreads();
+      // no barrier here: the next chunk's first LDS writes (its cell values)
+      // go to positions whose readers other than the writing lane all passed
+      // this chunk's second barrier, and its faces are written after its own
+      // first barrier, which every lane reaches only once done with this
+      // chunk's update
     };
 
     // the five moment sums of this lane's cell live in LDS (registers are
