@@ -217,6 +217,12 @@ __device__ inline void feq_coefficients(Real n, Real T, Real gamma, Real u, Real
   feq_scale<Real, QPT, NVT>(n, T, T0, nv, D);
 }
 
+// Sign bit of a value as an integer test: on a wave-uniform value held in a
+// scalar register this stays on the scalar unit (a float comparison would be a
+// vector instruction).
+__device__ inline bool sign_bit(float x) { return (__float_as_uint(x) >> 31) != 0u; }
+__device__ inline bool sign_bit(double x) { return (static_cast<uint64_t>(__double_as_longlong(x)) >> 63) != 0u; }
+
 // Fifth-order WENO (Jiang-Shu) value at the face between v3 and v4 from the
 // upwind-ordered values v1..v5:  H = sum_r w_r q_r with the candidate values
 // q_r of the three 3-point stencils and the weights w_r = a_r / sum(a),

@@ -209,8 +209,9 @@ hipError_t launch_combine(const TubeDev* tubes, const WorkItem* items, int nitem
 // q_phi - k carry equal values for data with u^y = 0).  State F[s][z][ldx],
 // records rec[9][z][ldx] (N0, Nx, Nz, T00, T0x, T0z, Txx, Txz, Tzz).
 // Velocity table row per (j, k): v_x, v_z, then the weighted moment factors
-// w, w v_x, w v_z, w v_x^2, w v_x v_z, w v_z^2 with w = w_xi[j] omega[k].
-constexpr int kVStride = 8;
+// w, w v_x, w v_z, w v_x^2, w v_x v_z, w v_z^2 with w = w_xi[j] omega[k], then
+// the advection factors -v_x/dx and -v_z/dz (and two unused entries).
+constexpr int kVStride = 12;
 constexpr int kPlaneTileX = 64, kPlaneTileZ = 4;  // cells per workgroup (init, moments)
 
 struct PlaneDev {

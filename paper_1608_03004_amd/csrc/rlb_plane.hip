@@ -192,7 +192,7 @@ void plane_stage_kernel(PlaneArgs<Real> a) {
   const cptr<double> itab = as_const(a.itab);
   const int stage = a.stage;
   const Real cs = stage == 1 ? Real(1) : (stage == 2 ? Real(0.25) : Real(2.0 / 3.0));
-  const Real dt = Real(P->dt), dx_inv = Real(P->dx_inv), dz_inv = Real(P->dz_inv);
+  const Real dt = Real(P->dt);
   const Real eps4 = Real(4.0 * P->weno_eps);
   const int t = threadIdx.x, tx = t % kPlaneTileX, tz = t / kPlaneTileX;
   const int lane_off = tz * kLd + tx;
@@ -286,7 +286,9 @@ void plane_stage_kernel(PlaneArgs<Real> a) {
           //    that every SIMD carries the same share of them
           const cptr<Real> V = vtab + (j * qh + k) * kVStride;
           const Real vx = V[0], vz = V[1];
-          const bool ux = vx >= Real(0), uz = vz >= Real(0);
+          // upwind directions from the sign bits, on the scalar unit (no node
+          // component is a negative zero)
+          const bool ux = !sign_bit(vx), uz = !sign_bit(vz);
           const Real* T = L + lane_off;
           L[kFxOff + lane_off] = face<Real, 1>(T + 3 * kLd, ux, eps4);
           L[kFzOff + lane_off] = face<Real, kLd>(T + 3, uz, eps4);
@@ -301,7 +303,7 @@ void plane_stage_kernel(PlaneArgs<Real> a) {
           const Real hxl = L[kFxOff + lane_off], hxr = L[kFxOff + lane_off + 1];
           const Real hzl = L[kFzOff + lane_off], hzr = L[kFzOff + lane_off + kLd];
           const Real feq = horner<Real, NVT>(Am, vx * hx + vz * hz);
-          const Real adv = (hxr - hxl) * (-vx * dx_inv) + (hzr - hzl) * (-vz * dz_inv);
+          const Real adv = (hxr - hxl) * V[8] + (hzr - hzl) * V[9];
           const Real rate = g0 - vx * gx - vz * gz;
           const Real Lr = adv - rate * (fr - feq);
           // f^n + cs ((f_in - f^n) + dt L): one rounding at the scale of F

@@ -209,15 +209,19 @@ rlb_status rlb_plane_create(const rlb_plane_desc* desc, rlb_precision prec, rlb_
   P->prec = prec;
   P->rsize = prec == RLB_FP32 ? 4 : 8;
   const int qh = d.q_phi / 2 + 1;
-  // velocity table: v_x, v_z and the weighted moment factors per (j, k)
+  // velocity table: v_x, v_z, the weighted moment factors and the advection
+  // factors -v_x/dx, -v_z/dz per (j, k)
   const long double pi = 3.141592653589793238462643383279502884L;
+  const long double adv_x = -(long double)d.nx / ((long double)d.x_max - d.x_min),
+                    adv_z = -(long double)d.nz / ((long double)d.z_max - d.z_min);
   for (int j = 0; j < d.q_xi; ++j) {
     for (int k = 0; k < qh; ++k) {
       const long double c = std::cos(2.0L * pi * k / d.q_phi);
       const long double vz = xi[j], vx = std::sqrt(1.0L - vz * vz) * c;
       const bool single = (k == 0) || (2 * k == d.q_phi);
       const long double w = (long double)wxi[j] * (single ? 1.0L : 2.0L) / d.q_phi;
-      const long double row[kVStride] = {vx, vz, w, w * vx, w * vz, w * vx * vx, w * vx * vz, w * vz * vz};
+      const long double row[kVStride] = {vx, vz, w, w * vx, w * vz, w * vx * vx, w * vx * vz, w * vz * vz,
+                                         adv_x * vx, adv_z * vz, 0.0L, 0.0L};
       for (int q = 0; q < kVStride; ++q) P->vtab_d.push_back(double(row[q]));
     }
   }
