@@ -461,6 +461,28 @@ def test_full_size_high_order_window(torch_cuda, precision, tol):
     _window_check(dict(nx=1 << 18, q_xi=64, q_p=4, n_v=63, tau=1e-2), precision, 3, tol=tol)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_pipelined_high_order_stages_match_the_single_launch_bitwise(torch_cuda, precision):
+    # 2^18 cells, N_v = 63: in FP32 the default schedule pipelines the
+    # equilibrium pre-pass over two pieces of the work list, 64-cell tiles
+    # over eight, and graph replay captures the side stream's fork and the
+    # per-piece joins; a node-split launch (split_below above the tile count)
+    # runs the pre-pass unpipelined on the lattice's stream, as the FP64 form
+    # always does.  All four give the same bits.
+    params = [dict(nx=1 << 18, q_xi=64, q_p=4, n_v=63, tau=1e-2)]
+    runs = []
+    for sched in (dict(tile=256), dict(tile=256, split_below=1 << 30), dict(tile=64), dict(tile=256, graph_steps=2)):
+        print(f"pipelined high-order {precision} {sched}", flush=True)
+        lat = _lattice(params, precision=precision, schedule=sched)
+        lat.set_initial_state(MOVING_L, MOVING_R)
+        lat.step(4)
+        runs.append((lat.state_array(0), lat.moments(0)))
+        del lat
+    for state, mom in runs[1:]:
+        assert np.array_equal(state, runs[0][0])
+        assert np.array_equal(mom, runs[0][1])
+
+
 def test_autotuner_restores_state_and_keeps_results(torch_cuda, tmp_path):
     from paper_1608_03004_amd import autotune
     import workloads
