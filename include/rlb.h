@@ -147,8 +147,9 @@ rlb_status rlb_tube_defaults(rlb_tube_desc* desc);
  * same section); the grid and time step follow section Numerical results.
  * tubes: ntubes >= 1 descriptors (copied).  prec: arithmetic of the
  * distribution (the Landau matching and the moment records are always FP64).
- * flags: RLB_WITH_ADJOINT or 0 (RLB_WITH_ADJOINT with a tube of n_v > 7 is
- * RLB_ERR_INVALID_ARG).  *out receives the handle. */
+ * flags: RLB_WITH_ADJOINT or 0 (with RLB_WITH_ADJOINT the workspace also
+ * holds the adjoint's buffers, for every tube form).  *out receives the
+ * handle. */
 rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision prec, uint32_t flags,
                       rlb_lattice** out);
 rlb_status rlb_destroy(rlb_lattice* lat);

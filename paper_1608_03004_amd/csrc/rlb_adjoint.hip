@@ -189,6 +189,117 @@ __device__ inline void adj_reduce_block(const AdjArgs<Real>& a, int block) {
   ta[y] = (a.tau_init ? 0.0 : ta[y]) + a.cJ * taup_all;
 }
 
+// High-order form (n_v > 7).  The stage's equilibrium values are the
+// pre-pass's (the forward's kernel on the same records, so bit for bit those
+// the forward used); its adjoint runs through the even/odd tables of the
+// fused projection.  Per radial node the forward forms, over the pairs b,
+//   ce_j = sum_b Ze[j][b] E_b,  co_j = sum_b Zo[j][b] O_b   (j < half),
+//   F_j = (ce_j + co_j)/2,  F_j' = (ce_j - co_j)/2   (j' = q_xi - 1 - j; the
+//   middle node of an odd rule only F_j),
+//   E_b = pref (G(x_b) + G(-x_b)),  O_b = pref (G(x_b) - G(-x_b)),
+// so with W_j = dL/dF_j the pair adjoints are
+//   Ebar_b = sum_j Ze[j][b] (W_j + W_j')/2,  Obar_b = sum_j Zo[j][b] (W_j - W_j')/2
+// (W_j/2 for both at the middle node), and E_b, O_b go through the same chain
+// to (pref, r, gamma, u) as the low-order coefficients' adjoint.  The groups
+// split the points for W and the pairs for the chain; W of a node is shared
+// through LDS.
+template <typename Real>
+__device__ inline void adj_reduce_block_high(const AdjArgs<Real>& a, int block) {
+  __shared__ double wv[kMaxQxHigh][kRedCells];
+  __shared__ double acc[7][kRedCells];
+  const int lane = threadIdx.x % kRedCells, grp = threadIdx.x / kRedCells;
+  const TubeDev& tb = a.tubes[a.tube];
+  const int nx = tb.nx;
+  const int y = block * kRedCells + lane;
+  const bool valid = y < nx;
+  const int yc = valid ? y : nx - 1;
+  const int64_t ldx = tb.ldx;
+  const int qx = tb.qx, qp = tb.qp, np = tb.np, half = (qx + 1) / 2;
+  const cptr<Real> jtab = as_const(a.jtab) + int64_t(tb.jrow) * kJStride;
+  const cptr<double> itab = as_const(a.itab) + int64_t(tb.irow) * kIStride;
+  const cptr<double> zt = as_const(a.ztab) + tb.z_off;
+  const int zj = tb.zj, zb = tb.zb;
+  double m[5];
+  for (int c = 0; c < 5; ++c) m[c] = a.rec_g[tb.rec_off + c * ldx + yc];
+  const Macro M = landau(m);
+  const double tau_inv = tb.tau_inv;
+  const Real g0 = Real(M.gamma * tau_inv), g1 = Real(M.u * tau_inv);
+  const double pref = M.n / (4.0 * M.T * tb.T0 * tb.T0), r = M.T / tb.T0;
+  const Real* g = a.g + tb.f_off;
+  const Real* K = a.K + tb.f_off;
+  const Real* feq = a.feq + tb.f_off;
+  // per-group partial sums: gamma-bar and u-bar of the rate, d/dtau, and the
+  // projection's prefb, rb, gamma-bar, u-bar
+  double part[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int i = 0; i < qp; ++i) {
+    for (int j = grp; j < qx; j += kRedGroups) {
+      const int64_t row = int64_t(i * qx + j) * ldx;
+      const Real xi = jtab[j * kJStride];
+      const double Kv = double(K[row + yc]);
+      const double diff = double(g[row + yc]) - double(feq[row + yc]);
+      const double rho = double(g0 - xi * g1);
+      part[0] -= Kv * diff * tau_inv;
+      part[1] += Kv * double(xi) * diff * tau_inv;
+      const double kr = Kv * rho;
+      part[2] += kr * tau_inv * diff;
+      wv[j][lane] = kr;
+    }
+    __syncthreads();
+    const cptr<double> L = itab + i * kIStride + 4;
+    for (int b = grp; b < zb; b += kRedGroups) {
+      double ev = 0.0, od = 0.0;
+      for (int j = 0; j < half; ++j) {
+        const int jm = qx - 1 - j;
+        const double wj = wv[j][lane];
+        const double ce = jm == j ? 0.5 * wj : 0.5 * (wj + wv[jm][lane]);
+        const double co = jm == j ? 0.5 * wj : 0.5 * (wj - wv[jm][lane]);
+        ev += zt[j * zb + b] * ce;
+        od += zt[(zj + j) * zb + b] * co;
+      }
+      const double xa = zt[2 * zj * zb + b];
+      const double yp = 1.0 / (M.gamma - xa * M.u), ym = 1.0 / (M.gamma + xa * M.u);
+      const double qpl = 1.0 - r * yp, qmi = 1.0 - r * ym;
+      double sp = L[np], dsp = 0.0, sm = L[np], dsm = 0.0;
+      for (int l = np - 1; l >= 0; --l) {
+        dsp = dsp * qpl + sp;
+        sp = sp * qpl + L[l];
+        dsm = dsm * qmi + sm;
+        sm = sm * qmi + L[l];
+      }
+      const double yp2 = yp * yp, ym2 = ym * ym;
+      const double gp = yp2 * sp, gm = ym2 * sm;
+      part[3] += ev * (gp + gm) + od * (gp - gm);
+      const double gpb = pref * (ev + od), gmb = pref * (ev - od);
+      double ypb = gpb * 2.0 * yp * sp, ymb = gmb * 2.0 * ym * sm;
+      const double qpb = gpb * yp2 * dsp, qmb = gmb * ym2 * dsm;
+      part[4] -= qpb * yp + qmb * ym;
+      ypb -= qpb * r;
+      ymb -= qmb * r;
+      part[5] -= ypb * yp2 + ymb * ym2;
+      part[6] += ypb * xa * yp2 - ymb * xa * ym2;
+    }
+    __syncthreads();  // wv is rewritten for the next node
+  }
+  combine_groups<7>(acc, part, grp, lane);
+  if (grp != 0 || !valid) return;
+  double nb = 0.0, Tb = 0.0;
+  feq_adjoint_finish(M.n, M.T, tb.T0, acc[3][lane], acc[4][lane], nb, Tb);
+  const double gb = acc[0][lane] + acc[5][lane], ub = acc[1][lane] + acc[6][lane];
+  double mu[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  landau_adjoint(m, M, 0.0, 0.0, gb, ub, nb, Tb, mu);
+  double* cb = a.cellbuf + 7 * tb.cell_off;
+  for (int c = 0; c < 5; ++c) cb[c * ldx + y] = mu[c];
+  cb[5 * ldx + y] = double(g0);
+  cb[6 * ldx + y] = double(g1);
+  double* ta = a.tau_acc + tb.cell_off;
+  ta[y] = (a.tau_init ? 0.0 : ta[y]) + a.cJ * acc[2][lane];
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void adj_reduce_high_kernel(AdjArgs<Real> a) {
+  adj_reduce_block_high<Real>(a, blockIdx.x);
+}
+
 template <typename Real>
 __device__ inline void adj_faces_block(const AdjArgs<Real>& a, int bx, int s) {
   const TubeDev& tb = a.tubes[a.tube];
@@ -388,10 +499,116 @@ __global__ void init_adjoint_final_kernel(const TubeDev* tubes, int tube, const 
   grad_out[3 * side + 2] = ub + gb * u / gamma;     // dL/du
 }
 
+// High-order form, pass 1: per block and side the sums over the block's
+// cells of lambda0 at every point (i, j), row c = i q_xi + j, in cell order.
+template <typename Real>
+__global__ __launch_bounds__(256) void init_adjoint_partial_high_kernel(const TubeDev* tubes, int tube,
+                                                                        const Real* lambda0, double* partials,
+                                                                        int part_stride) {
+  const TubeDev& tb = tubes[tube];
+  const int x0 = blockIdx.x * 256, x1 = min(x0 + 256, tb.nx);
+  const Real* lam = lambda0 + tb.f_off;
+  const int nc = tb.qp * tb.qx;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+    double v[2] = {0.0, 0.0};
+    const Real* row = lam + int64_t(c) * tb.ldx;
+    for (int x = x0; x < x1; ++x) v[left_of_split(tb, x) ? 0 : 1] += double(row[x]);
+    partials[(int64_t(blockIdx.x) * 2 + 0) * part_stride + c] = v[0];
+    partials[(int64_t(blockIdx.x) * 2 + 1) * part_stride + c] = v[1];
+  }
+}
+
+// High-order form, pass 2: one workgroup per side sums the block partials in
+// order into the point weights W of the side's (uniform) equilibrium, then
+// applies the adjoint of the fused projection (as in the stage's reduction;
+// the threads split the (node, pair) products and their partial sums are added
+// in thread order) and of (P, n, u) -> (n, T = P/n, gamma, u).
+__global__ __launch_bounds__(256) void init_adjoint_final_high_kernel(const TubeDev* tubes, int tube,
+                                                                      const double* itab_all, const double* ztab,
+                                                                      const double* sides, const double* partials,
+                                                                      int nblocks, int part_stride,
+                                                                      double* grad_out) {
+  __shared__ double W[kMaxQp * kMaxQxHigh];
+  __shared__ double red[4][256];
+  const int side = blockIdx.x, t = threadIdx.x;
+  const TubeDev& tb = tubes[tube];
+  const int qx = tb.qx, qp = tb.qp, np = tb.np, half = (qx + 1) / 2, nc = qp * qx;
+  for (int c = t; c < nc; c += blockDim.x) {
+    double v = 0.0;
+    for (int b = 0; b < nblocks; ++b) v += partials[(int64_t(b) * 2 + side) * part_stride + c];
+    W[c] = v;
+  }
+  __syncthreads();
+  const double* st = sides + 6 * tube + 3 * side;
+  const double P = st[0], n = st[1], u = st[2];
+  const double T = P / n, gamma = sqrt(1.0 + u * u);
+  const double pref = n / (4.0 * T * tb.T0 * tb.T0), r = T / tb.T0;
+  const double* zt = ztab + tb.z_off;
+  const int zj = tb.zj, zb = tb.zb;
+  double part[4] = {0.0, 0.0, 0.0, 0.0};  // prefb, rb, gamma-bar, u-bar
+  for (int pb = t; pb < qp * zb; pb += blockDim.x) {
+    const int i = pb / zb, b = pb % zb;
+    const double* Wi = W + i * qx;
+    double ev = 0.0, od = 0.0;
+    for (int j = 0; j < half; ++j) {
+      const int jm = qx - 1 - j;
+      const double ce = jm == j ? 0.5 * Wi[j] : 0.5 * (Wi[j] + Wi[jm]);
+      const double co = jm == j ? 0.5 * Wi[j] : 0.5 * (Wi[j] - Wi[jm]);
+      ev += zt[j * zb + b] * ce;
+      od += zt[(zj + j) * zb + b] * co;
+    }
+    const double* L = itab_all + int64_t(tb.irow + i) * kIStride + 4;
+    const double xa = zt[2 * zj * zb + b];
+    const double yp = 1.0 / (gamma - xa * u), ym = 1.0 / (gamma + xa * u);
+    const double qpl = 1.0 - r * yp, qmi = 1.0 - r * ym;
+    double sp = L[np], dsp = 0.0, sm = L[np], dsm = 0.0;
+    for (int l = np - 1; l >= 0; --l) {
+      dsp = dsp * qpl + sp;
+      sp = sp * qpl + L[l];
+      dsm = dsm * qmi + sm;
+      sm = sm * qmi + L[l];
+    }
+    const double yp2 = yp * yp, ym2 = ym * ym;
+    const double gp = yp2 * sp, gm = ym2 * sm;
+    part[0] += ev * (gp + gm) + od * (gp - gm);
+    const double gpb = pref * (ev + od), gmb = pref * (ev - od);
+    double ypb = gpb * 2.0 * yp * sp, ymb = gmb * 2.0 * ym * sm;
+    const double qpb = gpb * yp2 * dsp, qmb = gmb * ym2 * dsm;
+    part[1] -= qpb * yp + qmb * ym;
+    ypb -= qpb * r;
+    ymb -= qmb * r;
+    part[2] -= ypb * yp2 + ymb * ym2;
+    part[3] += ypb * xa * yp2 - ymb * xa * ym2;
+  }
+  for (int q = 0; q < 4; ++q) red[q][t] = part[q];
+  __syncthreads();
+  if (t != 0) return;
+  double tot[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < int(blockDim.x); ++k)
+    for (int q = 0; q < 4; ++q) tot[q] += red[q][k];
+  double nb = 0.0, Tb = 0.0;
+  feq_adjoint_finish(n, T, tb.T0, tot[0], tot[1], nb, Tb);
+  const double gb = tot[2], ub = tot[3];
+  grad_out[3 * side + 0] = Tb / n;                  // dL/dP
+  grad_out[3 * side + 1] = nb - Tb * P / (n * n);   // dL/dn
+  grad_out[3 * side + 2] = ub + gb * u / gamma;     // dL/du
+}
+
 template <typename Real, int QPT, int NVT>
 hipError_t adjoint_stage_t(int nx, int Q, const AdjArgs<Real>& a, hipStream_t s) {
   const int nred = (nx + kRedCells - 1) / kRedCells, nfx = (nx + 1 + 255) / 256;
   hipLaunchKernelGGL((adj_reduce_faces_kernel<Real, QPT, NVT>), dim3(nred + nfx * Q), dim3(256), 0, s, a, nred, nfx);
+  hipLaunchKernelGGL(adj_combine_kernel<Real>, dim3((nx + 255) / 256, Q), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// The high-order form: its reduction in a launch of its own (64 KB of LDS
+// for the weights of a node), then the face blocks alone and the combine.
+template <typename Real>
+hipError_t adjoint_stage_high(int nx, int Q, const AdjArgs<Real>& a, hipStream_t s) {
+  const int nred = (nx + kRedCells - 1) / kRedCells, nfx = (nx + 1 + 255) / 256;
+  hipLaunchKernelGGL(adj_reduce_high_kernel<Real>, dim3(nred), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((adj_reduce_faces_kernel<Real, 3, 5>), dim3(nfx * Q), dim3(256), 0, s, a, 0, nfx);
   hipLaunchKernelGGL(adj_combine_kernel<Real>, dim3((nx + 255) / 256, Q), dim3(256), 0, s, a);
   return hipGetLastError();
 }
@@ -402,6 +619,7 @@ hipError_t adjoint_stage_real(int qpt, int nvt, int nx, int Q, const void* args,
   if (qpt == 3 && nvt == 5) return adjoint_stage_t<Real, 3, 5>(nx, Q, a, s);
   if (qpt == 4 && nvt == 5) return adjoint_stage_t<Real, 4, 5>(nx, Q, a, s);
   if (qpt == 8 && nvt == 7) return adjoint_stage_t<Real, 8, 7>(nx, Q, a, s);
+  if (nvt == kNvtHigh) return adjoint_stage_high<Real>(nx, Q, a, s);
   return hipErrorInvalidValue;
 }
 
@@ -419,8 +637,17 @@ hipError_t initial_adjoint_t(const TubeDev* tubes, int tube, int nx, const void*
 
 template <typename Real>
 hipError_t initial_adjoint_real(int qpt, int nvt, const TubeDev* tubes, int tube, int nx, const void* jtab,
-                                const double* itab, const double* aux_d, int aux_pairs, const double* sides,
-                                const void* lambda0, double* partials, double* grad_out, hipStream_t s) {
+                                const double* itab, const double* aux_d, int aux_pairs, const double* ztab,
+                                const double* sides, const void* lambda0, double* partials, int part_stride,
+                                double* grad_out, hipStream_t s) {
+  if (nvt == kNvtHigh) {
+    const int nblocks = (nx + 255) / 256;
+    hipLaunchKernelGGL(init_adjoint_partial_high_kernel<Real>, dim3(nblocks), dim3(256), 0, s, tubes, tube,
+                       static_cast<const Real*>(lambda0), partials, part_stride);
+    hipLaunchKernelGGL(init_adjoint_final_high_kernel, dim3(2), dim3(256), 0, s, tubes, tube, itab, ztab, sides,
+                       partials, nblocks, part_stride, grad_out);
+    return hipGetLastError();
+  }
   if (qpt == 3 && nvt == 5)
     return initial_adjoint_t<Real, 3, 5>(tubes, tube, nx, jtab, itab, aux_d, aux_pairs, sides, lambda0, partials,
                                          grad_out, s);
@@ -461,13 +688,13 @@ hipError_t launch_fields_adjoint(int prec_fp32, const TubeDev* tubes, int tube, 
 
 hipError_t launch_initial_adjoint(int prec_fp32, int qpt, int nvt, const TubeDev* tubes, int tube, int nx,
                                   const void* jtab, const double* itab, const double* aux_d, int aux_pairs,
-                                  const double* sides, const void* lambda0, double* partials, int nblocks_max,
-                                  double* grad_out, hipStream_t stream) {
+                                  const double* ztab, const double* sides, const void* lambda0, double* partials,
+                                  int nblocks_max, int part_stride, double* grad_out, hipStream_t stream) {
   if ((nx + 255) / 256 > nblocks_max) return hipErrorInvalidValue;
-  return prec_fp32 ? initial_adjoint_real<float>(qpt, nvt, tubes, tube, nx, jtab, itab, aux_d, aux_pairs, sides,
-                                                 lambda0, partials, grad_out, stream)
-                   : initial_adjoint_real<double>(qpt, nvt, tubes, tube, nx, jtab, itab, aux_d, aux_pairs, sides,
-                                                  lambda0, partials, grad_out, stream);
+  return prec_fp32 ? initial_adjoint_real<float>(qpt, nvt, tubes, tube, nx, jtab, itab, aux_d, aux_pairs, ztab,
+                                                 sides, lambda0, partials, part_stride, grad_out, stream)
+                   : initial_adjoint_real<double>(qpt, nvt, tubes, tube, nx, jtab, itab, aux_d, aux_pairs, ztab,
+                                                  sides, lambda0, partials, part_stride, grad_out, stream);
 }
 
 }  // namespace rlb

@@ -72,11 +72,13 @@ struct rlb_lattice {
          off_mask = 0, off_flag = 0, off_fields = 0, off_totals = 0, total = 0;
   size_t off_part = 0;  // per-node sums of split launches (0: none)
   size_t off_ztab = 0, off_feq = 0;  // high-order tables and equilibrium values (0: none)
+  size_t off_afeq = 0;  // the adjoint's equilibrium values (high-order with RLB_WITH_ADJOINT)
   int part_stride = 0;  // doubles per cell in that buffer
   size_t step_bytes = 0;  // bytes of the layout before f^n (see rlb_create)
   // adjoint workspace (RLB_WITH_ADJOINT)
   int64_t cell_elems = 0, face_elems = 0;
   int init_blocks_max = 0;
+  int ipart_stride = kMaxQp * (kMaxNv + 1);  // doubles per block and side of the initial adjoint's partials
   size_t off_aF[2] = {0, 0}, off_arec[3] = {0, 0, 0}, off_lam2 = 0, off_lam1 = 0, off_acc = 0, off_G = 0,
          off_cellbuf = 0, off_tauacc = 0, off_ipart = 0, off_grad = 0;
 
@@ -535,8 +537,6 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
     if (!rlb::weno_eps_in_range(tubes[k].weno_eps, prec == RLB_FP32))
       return fail(nullptr, RLB_ERR_INVALID_ARG,
                   "tube " + std::to_string(k) + ": weno_eps must lie in [1e-40, 1e30] (FP32) or [1e-300, 1e30] (FP64)");
-    if ((flags & RLB_WITH_ADJOINT) && tubes[k].n_v > kMaxNv)
-      return fail(nullptr, RLB_ERR_INVALID_ARG, "the adjoint supports n_v <= 7 only");
   }
   rlb_lattice* L = new rlb_lattice();
   L->desc.assign(tubes, tubes + ntubes);
@@ -636,6 +636,7 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
     td.face_off = L->face_elems;
     L->face_elems += int64_t(d.q_xi) * d.q_p * td.ldf;
     L->init_blocks_max = std::max(L->init_blocks_max, (d.nx + 255) / 256);
+    if (d.n_v > kMaxNv) L->ipart_stride = std::max(L->ipart_stride, d.q_p * d.q_xi);
     f_off += int64_t(d.q_xi) * d.q_p * td.ldx;
     rec_off += 5 * int64_t(td.ldx);
     L->max_ldx = std::max(L->max_ldx, td.ldx);
@@ -706,7 +707,10 @@ rlb_status rlb_create(const rlb_tube_desc* tubes, int32_t ntubes, rlb_precision 
     L->off_G = o; o = align256(o + 5 * size_t(L->face_elems) * L->rsize);
     L->off_cellbuf = o; o = align256(o + 7 * size_t(L->cell_elems) * 8);
     L->off_tauacc = o; o = align256(o + size_t(L->cell_elems) * 8);
-    L->off_ipart = o; o = align256(o + size_t(L->init_blocks_max) * 2 * kMaxQp * (kMaxNv + 1) * 8);
+    L->off_ipart = o; o = align256(o + size_t(L->init_blocks_max) * 2 * L->ipart_stride * 8);
+    // a buffer of its own, so that a forward recompute on another stream
+    // (the segment halves) never overwrites the values an adjoint stage reads
+    if (L->has_high) { L->off_afeq = o; o = align256(o + L->state_elems * L->rsize); }
     L->off_grad = o; o = align256(o + 8 * 8);
   }
   L->total = o;
@@ -1136,6 +1140,8 @@ rlb_status adjoint_stage(rlb_lattice* L, int tube, int qpt, int nvt, const void*
   a.add_acc = add_acc;
   a.acc_init = acc_init;
   a.tau_init = tau_init;
+  a.feq = L->off_afeq ? L->dev<Real>(L->off_afeq) : nullptr;
+  a.ztab = L->has_high ? L->dev<double>(L->off_ztab) : nullptr;
   const TubeDev& td = L->tubes[tube];
   hipError_t e = launch_adjoint_stage(L->prec == RLB_FP32 ? 1 : 0, qpt, nvt, td.nx, td.qx * td.qp, &a, L->stream);
   if (e != hipSuccess) return hip_fail(L, e, "adjoint kernel launch");
@@ -1166,24 +1172,40 @@ rlb_status adjoint_of_step(rlb_lattice* L, const void* Fn, const void* F1, const
   void* acc = L->ws + L->off_acc;
   const bool fp32 = L->prec == RLB_FP32;
   for (const Group& g : L->groups) {
-    for (int it = g.item_begin; it < g.item_end; ++it) {
-      if (L->items[it].x0 != 0) continue;  // one pass per tube
-      const int t = L->items[it].tube;
-      const double dt = L->tubes[t].dt;
-      auto stage = [&](const void* gs, const double* rec, const void* K, void* out, const void* ain, void* aout,
-                       double cK, double cJ, double cA, int add_acc, int acc_init, int tau_init) {
-        return fp32 ? adjoint_stage<float>(L, t, g.qpt, g.nvt, gs, rec, K, out, ain, aout, cK, cJ, cA, add_acc,
-                                           acc_init, tau_init)
-                    : adjoint_stage<double>(L, t, g.qpt, g.nvt, gs, rec, K, out, ain, aout, cK, cJ, cA, add_acc,
-                                            acc_init, tau_init);
-      };
-      // f^{n+1} = 1/3 f^n + 2/3 (f2 + dt L(f2))
-      if ((st = stage(F2, r2, lambda, lam2, nullptr, acc, 2.0 / 3.0, 2.0 / 3.0 * dt, 1.0 / 3.0, 0, 1, 1)) != RLB_OK)
+    const bool high = g.nvt == kNvtHigh;
+    std::vector<int> tubes;  // one pass per tube
+    for (int it = g.item_begin; it < g.item_end; ++it)
+      if (L->items[it].x0 == 0) tubes.push_back(L->items[it].tube);
+    auto stage = [&](int t, const void* gs, const double* rec, const void* K, void* out, const void* ain, void* aout,
+                     double cK, double cJ, double cA, int add_acc, int acc_init, int tau_init) {
+      return fp32 ? adjoint_stage<float>(L, t, g.qpt, g.nvt, gs, rec, K, out, ain, aout, cK, cJ, cA, add_acc,
+                                         acc_init, tau_init)
+                  : adjoint_stage<double>(L, t, g.qpt, g.nvt, gs, rec, K, out, ain, aout, cK, cJ, cA, add_acc,
+                                          acc_init, tau_init);
+    };
+    // the high-order group's equilibrium values of a stage's input, for all of
+    // its tubes, by the forward's pre-pass (so bit for bit the forward's)
+    auto equilibrium_of = [&](const double* rec) -> rlb_status {
+      if (!high) return RLB_OK;
+      const hipError_t e = fp32 ? equilibrium_pass<float>(L, g, rec, L->ws + L->off_afeq, L->stream)
+                                : equilibrium_pass<double>(L, g, rec, L->ws + L->off_afeq, L->stream);
+      return e == hipSuccess ? RLB_OK : hip_fail(L, e, "equilibrium pre-pass launch");
+    };
+    // f^{n+1} = 1/3 f^n + 2/3 (f2 + dt L(f2))
+    if ((st = equilibrium_of(r2)) != RLB_OK) return st;
+    for (int t : tubes)
+      if ((st = stage(t, F2, r2, lambda, lam2, nullptr, acc, 2.0 / 3.0, 2.0 / 3.0 * L->tubes[t].dt, 1.0 / 3.0, 0, 1,
+                      1)) != RLB_OK)
         return st;
-      // f2 = 3/4 f^n + 1/4 (f1 + dt L(f1))
-      if ((st = stage(F1, r1, lam2, lam1, acc, acc, 0.25, 0.25 * dt, 0.75, 0, 0, 0)) != RLB_OK) return st;
-      // f1 = f^n + dt L(f^n)
-      if ((st = stage(Fn, r0, lam1, lambda, acc, nullptr, 1.0, dt, 0.0, 1, 0, 0)) != RLB_OK) return st;
+    // f2 = 3/4 f^n + 1/4 (f1 + dt L(f1))
+    if ((st = equilibrium_of(r1)) != RLB_OK) return st;
+    for (int t : tubes)
+      if ((st = stage(t, F1, r1, lam2, lam1, acc, acc, 0.25, 0.25 * L->tubes[t].dt, 0.75, 0, 0, 0)) != RLB_OK)
+        return st;
+    // f1 = f^n + dt L(f^n)
+    if ((st = equilibrium_of(r0)) != RLB_OK) return st;
+    for (int t : tubes) {
+      if ((st = stage(t, Fn, r0, lam1, lambda, acc, nullptr, 1.0, L->tubes[t].dt, 0.0, 1, 0, 0)) != RLB_OK) return st;
       hipError_t e = launch_tau_reduce(L->dev<TubeDev>(L->off_tubes), t, L->dev<double>(L->off_tauacc), dL_dtau,
                                        L->stream);
       if (e != hipSuccess) return hip_fail(L, e, "tau reduction launch");
@@ -1332,8 +1354,9 @@ rlb_status rlb_initial_state_adjoint(rlb_lattice* L, int32_t tube, const void* l
   double* grad = L->dev<double>(L->off_grad);
   hipError_t e = launch_initial_adjoint(L->prec == RLB_FP32 ? 1 : 0, qpt, nvt, L->dev<TubeDev>(L->off_tubes), tube,
                                         L->tubes[tube].nx, L->ws + L->off_jtab, L->dev<double>(L->off_itab),
-                                        L->dev<double>(L->off_aux_d), L->aux_pairs, L->dev<double>(L->off_sides),
-                                        lambda0, L->dev<double>(L->off_ipart), L->init_blocks_max, grad, L->stream);
+                                        L->dev<double>(L->off_aux_d), L->aux_pairs, L->dev<double>(L->off_ztab),
+                                        L->dev<double>(L->off_sides), lambda0, L->dev<double>(L->off_ipart),
+                                        L->init_blocks_max, L->ipart_stride, grad, L->stream);
   if (e != hipSuccess) return hip_fail(L, e, "initial-state adjoint launch");
   double h[6];
   HIP_TRY(L, hipMemcpyAsync(h, grad, sizeof h, hipMemcpyDeviceToHost, L->stream));

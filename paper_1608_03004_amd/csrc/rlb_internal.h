@@ -110,6 +110,10 @@ struct AdjArgs {
   int64_t G_slot;   // elements per slot
   double cK, cJ, cA;
   int32_t add_acc, acc_init, tau_init;
+  // high-order form: the pre-pass's equilibrium values of the stage input g
+  // (state layout) and the even/odd projection tables
+  const Real* feq;
+  const double* ztab;
 };
 
 // Work item of the stage kernels: a tile of cells of one tube.
@@ -298,10 +302,12 @@ hipError_t launch_tau_reduce(const TubeDev* tubes, int tube, const double* tau_a
 hipError_t launch_fields_adjoint(int prec_fp32, const TubeDev* tubes, int tube, int nx, const void* jtab,
                                  const double* itab, const double* rec, const double* dfields, int64_t ld,
                                  void* lambda, hipStream_t stream);
+// partials: nblocks_max x 2 x part_stride doubles (part_stride >= QPT (NVT + 1)
+// of the low-order groups and >= q_p q_xi of a high-order tube).
 hipError_t launch_initial_adjoint(int prec_fp32, int qpt, int nvt, const TubeDev* tubes, int tube, int nx,
                                   const void* jtab, const double* itab, const double* aux_d, int aux_pairs,
-                                  const double* sides, const void* lambda0, double* partials, int nblocks_max,
-                                  double* grad_out, hipStream_t stream);
+                                  const double* ztab, const double* sides, const void* lambda0, double* partials,
+                                  int nblocks_max, int part_stride, double* grad_out, hipStream_t stream);
 
 // Allocation-free step (rlb_noalloc.hip, host side in rlb_api.cpp): bytes of
 // scratch a lattice's step needs besides its state, and the steps themselves

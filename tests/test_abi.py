@@ -150,9 +150,9 @@ def test_plane_weno_epsilon_range(lib, eps, prec, ok):
         lib.rlb_plane_destroy(ph)
 
 
-def test_high_order_tubes_create_without_adjoint(lib):
+def test_high_order_tubes_create_with_and_without_adjoint(lib):
     # 7 < n_v < q_xi <= 256: the matrix-core equilibrium form; it adds one
-    # state-sized equilibrium buffer to the workspace and has no adjoint
+    # state-sized equilibrium buffer to the workspace (and the adjoint one more)
     low = [rlb.Tube(nx=300, q_xi=64, q_p=4)]
     high = [rlb.Tube(nx=300, q_xi=64, q_p=4, n_v=63), rlb.Tube(nx=50, q_xi=9, q_p=2, n_v=8, n_p=1),
             rlb.Tube(nx=70, q_xi=128, q_p=3, n_v=127), rlb.Tube(nx=20, q_xi=256, q_p=3, n_v=255)]
@@ -172,9 +172,20 @@ def test_high_order_tubes_create_without_adjoint(lib):
     h = ctypes.c_void_p()
     assert lib.rlb_create(arr, 4, rlb.RLB_FP32, 0, ctypes.byref(h)) == 0
     lib.rlb_destroy(h)
+    # the adjoint covers the high-order form: its workspace adds the adjoint's
+    # buffers, among them a second state-sized array of equilibrium values
     h = ctypes.c_void_p()
-    assert lib.rlb_create(arr, 4, rlb.RLB_FP64, rlb.RLB_WITH_ADJOINT, ctypes.byref(h)) == rlb.RLB_ERR_INVALID_ARG
-    assert not h.value and b"n_v <= 7" in lib.rlb_last_error(None)
+    assert lib.rlb_create(arr, 4, rlb.RLB_FP64, 0, ctypes.byref(h)) == 0
+    plain = ctypes.c_size_t()
+    lib.rlb_workspace_size(h, ctypes.byref(plain))
+    lib.rlb_destroy(h)
+    h = ctypes.c_void_p()
+    assert lib.rlb_create(arr, 4, rlb.RLB_FP64, rlb.RLB_WITH_ADJOINT, ctypes.byref(h)) == 0
+    adj = ctypes.c_size_t()
+    lib.rlb_workspace_size(h, ctypes.byref(adj))
+    state = sum(t.q_xi * t.q_p * ((t.nx + 63) // 64 * 64) for t in high) * 8
+    assert adj.value >= plain.value + 6 * state
+    lib.rlb_destroy(h)
 
 
 @pytest.mark.parametrize("q_xi,q_p", [(2, 3), (5, 3), (8, 3), (64, 4), (128, 3), (200, 5), (256, 4)])

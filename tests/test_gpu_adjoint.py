@@ -41,6 +41,11 @@ CASES = [
     dict(nx=40, q_xi=7, q_p=5, n_p=3, n_v=7, tau=3e-2),       # generic group
     dict(nx=80, q_xi=8, q_p=3, tau=1e-2, T0=0.8),
     dict(nx=300, q_xi=4, q_p=3, tau=1e-3),                    # several tiles
+    # the high-order form (n_v > 7): equilibrium from the matrix-core pre-pass
+    dict(nx=48, q_xi=16, q_p=3, n_v=15, tau=1e-2),
+    dict(nx=36, q_xi=9, q_p=3, n_v=8, tau=2e-2),              # odd q_xi: the middle node
+    dict(nx=40, q_xi=64, q_p=3, n_v=63, tau=2e-2),            # largest two-tile form
+    dict(nx=24, q_xi=128, q_p=3, n_v=127, tau=2e-2),          # four row tiles
 ]
 
 
@@ -94,10 +99,13 @@ def test_adjoint_of_collisionless_step_is_the_transposed_stencil(torch_cuda):
     assert float(dtau[0]) == 0.0
 
 
-def test_fields_and_initial_state_adjoints(torch_cuda):
+@pytest.mark.parametrize("params", [dict(nx=120, q_xi=8, q_p=3, tau=1e-2),
+                                    dict(nx=120, q_xi=16, q_p=3, n_v=15, tau=1e-2),
+                                    dict(nx=300, q_xi=33, q_p=3, n_v=30, tau=1e-2)],
+                         ids=["low_order", "high_order", "high_order_odd_two_blocks"])
+def test_fields_and_initial_state_adjoints(torch_cuda, params):
     torch = torch_cuda
     from oracle import oracle as O
-    params = dict(nx=120, q_xi=8, q_p=3, tau=1e-2)
     t = oracle_tube(params)
     left, right = (1.0, 1.0, 0.3), (0.2, 0.4, -0.2)
     F = O.run(t, left, right, 10)
@@ -206,12 +214,15 @@ def test_fp32_adjoint_against_fp64_adjoint(torch_cuda):
     assert np.abs(g32 - g64).max() < 1e-3 * scale
 
 
+@pytest.mark.parametrize("params", [dict(nx=300, q_xi=12, q_p=3, tau=2e-2),
+                                    dict(nx=300, q_xi=32, q_p=3, n_v=31, tau=2e-2)], ids=["low_order", "high_order"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_adjoint_segment_equals_step_by_step_adjoint(torch_cuda, precision):
+def test_adjoint_segment_equals_step_by_step_adjoint(torch_cuda, precision, params):
     # One reverse sweep over a segment (stage states recomputed once and kept)
-    # against rlb_adjoint_step applied to each recomputed state in turn.
+    # against rlb_adjoint_step applied to each recomputed state in turn; the
+    # high-order form's forward recompute on a side stream writes its own
+    # equilibrium buffer, not the one the reverse half reads.
     torch = torch_cuda
-    params = dict(nx=300, q_xi=12, q_p=3, tau=2e-2)
     lat = _lattice([params], precision)
     lat.set_initial_state((1.0, 1.0, 0.1), (0.2, 0.3, -0.1))
     lat.step(4)
@@ -246,3 +257,22 @@ def test_adjoint_segment_equals_step_by_step_adjoint(torch_cuda, precision):
     assert torch.equal(lam_a, lam_c) and torch.equal(da, dc)
     # the lattice's own state is untouched by the sweep
     assert torch.equal(lat.tube_view(lat.get_state()), lat.tube_view(states[-1]))
+
+
+def test_high_order_profile_gradient_against_differences(torch_cuda):
+    # the gradient of the profile loss through the high-order form (Q = 32 x 3,
+    # N_v = 31, 60 steps) against central differences of the GPU forward
+    torch = torch_cuda
+    params = dict(nx=256, q_xi=32, q_p=3, n_v=31, tau=0.02, dt=0.5 / 256)
+    nsteps = 60
+    start = (0.02, 1.0, 1.0)
+    target = torch.linspace(0.3, 2.8, 256, dtype=torch.float64, device="cuda")
+    _, grad, _ = _loss_and_grad(params, nsteps, start, target, every=7)
+    print(f"[high-order adjoint grad] {grad}", flush=True)
+    for k in (0, 1):
+        h = 1e-6 * start[k]
+        tp = list(start); tp[k] += h
+        tm = list(start); tm[k] -= h
+        tgt = target.cpu().numpy()
+        fd = (_gpu_loss(params, nsteps, tp, tgt) - _gpu_loss(params, nsteps, tm, tgt)) / (2 * h)
+        assert abs(fd - grad[k]) < 1e-6 * abs(grad[k]), (k, fd, grad[k])
