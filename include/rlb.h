@@ -82,8 +82,9 @@ typedef enum { RLB_FP64 = 0, RLB_FP32 = 1 } rlb_precision;
  *   n_v, n_p  -- truncation orders of eq. feqtrunc (the paper uses 5 and 2);
  *                n_p < q_p;  n_v <= 7, or 7 < n_v < q_xi <= 256 (the
  *                high-order form: the equilibrium is evaluated by a
- *                matrix-core pre-pass into one more state-sized buffer; no
- *                adjoint);  N^mu and T^{mu nu} of the equilibrium are exact
+ *                matrix-core pre-pass into one more state-sized buffer, and
+ *                RLB_WITH_ADJOINT adds one for the adjoint's own pre-pass);
+ *                N^mu and T^{mu nu} of the equilibrium are exact
  *                when n_p + 2 <= 2 q_p - 1 and n_v + 2 <= 2 q_xi - 1, both
  *                required;
  *   tau       -- constant relaxation time (section Relativistic LB equation);
@@ -242,10 +243,12 @@ rlb_status rlb_tables(const rlb_lattice* lat, int32_t tube, double* xi, double* 
 
 /*
  * Discrete adjoint (reverse mode) of the time step, for gradients of a loss on
- * the final fields with respect to tau and the initial states.  The lattice
- * must have been created with RLB_WITH_ADJOINT.  All buffers are device
- * memory in the state layout (see above); all calls are asynchronous unless
- * noted.
+ * the final fields with respect to tau and the initial states, for every tube
+ * form: in the high-order form (n_v > 7) an adjoint stage re-evaluates its
+ * input's equilibrium with the forward's pre-pass and applies the transposed
+ * even/odd projection tables.  The lattice must have been created with
+ * RLB_WITH_ADJOINT.  All buffers are device memory in the state layout (see
+ * above); all calls are asynchronous unless noted.
  *
  * rlb_adjoint_step: lambda holds dL/df^{n+1} on entry and dL/df^n on return,
  *   where f^{n+1} is the step (3 stages) applied to state_n = f^n.  The two
