@@ -253,7 +253,7 @@ def batched_selection(w):
     return sorted(set(sel))
 
 
-def leg_batched(steps, schedule=None):
+def leg_batched(steps, schedule=None, full_steps=500):
     import torch
     import workloads
     from paper_1608_03004_amd import Lattice, Tube
@@ -279,8 +279,22 @@ def leg_batched(steps, schedule=None):
     for k in batched_selection(w):
         wins.append(window_request(f"sod_batched/tube{k}", w["tubes"][k], w["left"][k], w["right"][k],
                                    warm + steps, lat.info(k)["dt"], lat.moments(k)))
+    full = None
+    if full_steps and not schedule:
+        # the configuration's whole run (not in profiling runs): full_steps
+        # steps of every tube from its initial states, timed as one; no
+        # non-physical state may occur and e, n stay positive in every cell
+        import numpy as np
+        lat.set_initial_states(w["left"], w["right"])
+        wall_full, _ = timed_steps(lat, full_steps)
+        lat.check()
+        fl = lat.flags()
+        mins = np.array([lat.moments(k)[5:7].min(axis=1) for k in range(len(tubes))])
+        full = dict(steps=full_steps, value=pts * full_steps / wall_full, ms_per_step=1e3 * wall_full / full_steps,
+                    min_e=float(mins[:, 0].min()), min_n=float(mins[:, 1].min()), fast_flow=fl["fast_flow"])
+        progress(f"batched full run: {full_steps} steps in {wall_full:.2f} s")
     out = dict(value=pts * steps / wall, unit="cell*quad-point updates/s", ms_per_step=1e3 * wall / steps,
-               steps=steps, tubes=len(tubes), points_per_step=pts, schedule=lat.get_schedule(),
+               steps=steps, tubes=len(tubes), points_per_step=pts, schedule=lat.get_schedule(), full_run=full,
                roofline=roofline(tubes, 4, steps, ev, measured_traffic("sod_batched/fp32")),
                autotune_candidates=len(timings),
                autotune_top=[dict(json.loads(k), ms_per_step=round(v * 1e3, 3))
@@ -829,6 +843,8 @@ def main():
     ap.add_argument("--adjoint-fd", type=int, default=1, help="central-difference check of the FP64 gradients")
     ap.add_argument("--high-steps", type=int, default=20)
     ap.add_argument("--batched-steps", type=int, default=50)
+    ap.add_argument("--batched-full-steps", type=int, default=500,
+                    help="the batched configuration's whole run after the timed steps (0: none)")
     ap.add_argument("--ballistic-steps", type=int, default=20)
     ap.add_argument("--ballistic-full-steps", type=int, default=4000,
                     help="steps of the ballistic run checked against eq. ballistic (0: skip)")
@@ -888,7 +904,7 @@ def main():
         if args.batched_schedule:
             v = [int(x) for x in args.batched_schedule.split(",")]
             bs = dict(zip(("tile", "persistent", "blocks_per_cu", "graph_steps", "chunk", "split_below"), v))
-        line["batched"], wins = leg_batched(args.batched_steps, bs)
+        line["batched"], wins = leg_batched(args.batched_steps, bs, args.batched_full_steps)
         windows += wins
         progress("batched done")
     if "adjoint" in legs:
