@@ -42,12 +42,13 @@ def run_profile(nx, q_xi, tau, t_end, dt=None, precision="fp64", q_p=3):
     return f, t
 
 
-def shock_width(n, pre, lo=0.1, hi=0.9, plateau=(20, 8)):
+def shock_width(n, pre, lo=0.05, hi=0.95, plateau=(20, 8)):
     """Width in nodes of the right-moving shock in the density profile n.
 
     The shock is the right-most jump above the undisturbed state `pre`; the
     post-shock value is the median of the plateau `plateau` nodes behind it;
-    the width is the distance between the lo and hi crossings of the jump.
+    the width is the distance between the lo and hi crossings of the jump (by
+    default 5 % and 95 %: the paper gives a width without a definition).
     """
     above = np.where(n > pre + 0.5 * pre)[0]
     i_s = int(above.max())

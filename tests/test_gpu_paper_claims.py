@@ -29,8 +29,10 @@ def test_hydrodynamic_shock_is_a_few_nodes_wide(torch_cuda):
     run = GOLDEN["hydro_run"]["value"]
     res = E.hydro(nx=run["L_z"], t_end=0.2)
     print(f"[hydro] {res}", flush=True)
+    # the paper's range itself, for the width between the 5 % and 95 % crossings
+    # of the jump (the reading the paper leaves open; 10 %-90 % gives 5 nodes)
     lo, hi = GOLDEN["hydro_shock_width_nodes"]["value"]
-    assert lo - 3 <= res["shock_width_nodes"] <= hi + 5
+    assert lo <= res["shock_width_nodes"] <= hi
     # the post-shock density approaches the ideal P = e/3 value 0.2885 (hydro limit)
     from oracle import analytic as A
     st = A.riemann_star((1.0, 1.0, 0.0), (0.1, 0.125, 0.0))
