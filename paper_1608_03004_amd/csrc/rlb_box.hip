@@ -186,10 +186,12 @@ __device__ inline Real reg_face(Real p0, Real p1, Real p2, Real p3, Real p4, Rea
 // Occupancy: four waves per SIMD for FP32 with Q_p <= 4 (the LDS of four
 // workgroups fills a CU; a few per-cell values spill outside the point loop;
 // measured 2.45 against 3.05 ms per stage on a 128^3 box with Q = 192 with
-// the compiler's three waves); the other forms are left to the compiler.
+// the compiler's three waves) and three for FP64 with Q_p <= 4 (the per-cell
+// values spill, outside the point loop; 14.3 against 17.0 ms per step on that
+// box with the compiler's two); the generic group is left to the compiler.
 template <typename Real, int QPT>
 constexpr int box_waves_per_eu() {
-  return (sizeof(Real) == 4 && QPT <= 4) ? 4 : 1;
+  return (sizeof(Real) == 4 && QPT <= 4) ? 4 : (QPT <= 4 ? 3 : 1);
 }
 
 template <typename Real, int QPT, int NVT, bool HAS_FN>
