@@ -29,23 +29,28 @@ namespace {
 
 using namespace dev;
 
-// adj_reduce: a block holds kRedCells cells and kRedGroups groups of
-// kRedCells lanes (two groups per wave), one lane per cell in each group.  The
-// groups split the quadrature points of the reduction and the auxiliary node
-// pairs of the projection's adjoint; partial sums are combined through LDS in
-// a fixed group order, so the result is deterministic.  32 cells per block
-// doubles the blocks of a small tube over 64 (the adjoint is latency-bound at
-// its sizes: +9 % adjoint steps/s on 4096 cells x 96 points).
-constexpr int kRedCells = 32, kRedGroups = 8;
+// adj_reduce: a block of 256 threads holds red_cells() cells and 256 /
+// red_cells() groups of red_cells() lanes, one lane per cell in each group.
+// The groups split the quadrature points of the reduction and the auxiliary
+// node pairs of the projection's adjoint; partial sums are combined through
+// LDS in a fixed group order, so the result is deterministic.  The adjoint is
+// latency-bound at its sizes, so small blocks pay: on 4096 cells x 96 points,
+// 32 cells per block gave +9 % adjoint steps/s over 64 in FP64 and FP32, and
+// 16 cells another +7.7 % in FP32 (but -2 % in FP64).
+template <typename Real>
+constexpr int red_cells() {
+  return sizeof(Real) == 4 ? 16 : 32;
+}
 
 // acc[d][lane] = sum over groups (in group order) of part[d]; every group
 // reads the same combined values afterwards.  Ends with a barrier.  The groups
 // post kSlotVals values at a time and group g sums value g of the batch over
 // the groups, so a batch costs two barriers whatever the group count.
 constexpr int kSlotVals = 8;
-static_assert(kSlotVals <= kRedGroups, "one summing group per posted value");
-template <int N>
+template <int N, int kRedCells>
 __device__ inline void combine_groups(double (*acc)[kRedCells], const double* part, int grp, int lane) {
+  constexpr int kRedGroups = 256 / kRedCells;
+  static_assert(kSlotVals <= kRedGroups, "one summing group per posted value");
   __shared__ double slots[kRedGroups][kSlotVals][kRedCells];
 #pragma unroll
   for (int d0 = 0; d0 < N; d0 += kSlotVals) {
@@ -64,6 +69,7 @@ __device__ inline void combine_groups(double (*acc)[kRedCells], const double* pa
 
 template <typename Real, int QPT, int NVT>
 __device__ inline void adj_reduce_block(const AdjArgs<Real>& a, int block) {
+  constexpr int kRedCells = red_cells<Real>(), kRedGroups = 256 / kRedCells;
   constexpr int ND = QPT * (NVT + 1);
   __shared__ double acc[ND + 3][kRedCells];
   const int lane = threadIdx.x % kRedCells, grp = threadIdx.x / kRedCells;
@@ -161,7 +167,7 @@ __device__ inline void adj_reduce_block(const AdjArgs<Real>& a, int block) {
       }
     }
   }
-  combine_groups<ND + 3>(acc, red, grp, lane);
+  combine_groups<ND + 3, kRedCells>(acc, red, grp, lane);
   double Db[QPT][NVT + 1];
 #pragma unroll
   for (int i = 0; i < QPT; ++i)
@@ -174,7 +180,7 @@ __device__ inline void adj_reduce_block(const AdjArgs<Real>& a, int block) {
   double part[4] = {0.0, 0.0, 0.0, 0.0};  // prefb, rb, gamma-bar, u-bar
   feq_adjoint_sums<QPT, NVT>(M.n, M.T, M.gamma, M.u, tb.T0, qp, tb.np, tb.nv, itab, as_const(a.aux_d), a.aux_pairs,
                              grp, kRedGroups, Db, part[0], part[1], part[2], part[3]);
-  combine_groups<4>(acc, part, grp, lane);
+  combine_groups<4, kRedCells>(acc, part, grp, lane);
   if (grp != 0 || !valid) return;
   double nb = 0.0, Tb = 0.0;
   feq_adjoint_finish(M.n, M.T, tb.T0, acc[0][lane], acc[1][lane], nb, Tb);
@@ -205,6 +211,7 @@ __device__ inline void adj_reduce_block(const AdjArgs<Real>& a, int block) {
 // through LDS.
 template <typename Real>
 __device__ inline void adj_reduce_block_high(const AdjArgs<Real>& a, int block) {
+  constexpr int kRedCells = red_cells<Real>(), kRedGroups = 256 / kRedCells;
   __shared__ double wv[kMaxQxHigh][kRedCells];
   __shared__ double acc[7][kRedCells];
   const int lane = threadIdx.x % kRedCells, grp = threadIdx.x / kRedCells;
@@ -280,7 +287,7 @@ __device__ inline void adj_reduce_block_high(const AdjArgs<Real>& a, int block) 
     }
     __syncthreads();  // wv is rewritten for the next node
   }
-  combine_groups<7>(acc, part, grp, lane);
+  combine_groups<7, kRedCells>(acc, part, grp, lane);
   if (grp != 0 || !valid) return;
   double nb = 0.0, Tb = 0.0;
   feq_adjoint_finish(M.n, M.T, tb.T0, acc[3][lane], acc[4][lane], nb, Tb);
@@ -328,7 +335,6 @@ __device__ inline void adj_faces_block(const AdjArgs<Real>& a, int bx, int s) {
 // the incoming adjoint, so one launch runs both: its first `nred` blocks are
 // reduction blocks, the rest face blocks (nfx per point).  The face blocks
 // fill the CUs the reduction leaves idle at the adjoint's sizes.
-static_assert(kRedCells * kRedGroups == 256, "reduction and face blocks share the block size");
 template <typename Real, int QPT, int NVT>
 __global__ __launch_bounds__(256) void adj_reduce_faces_kernel(AdjArgs<Real> a, int nred, int nfx) {
   const int b = blockIdx.x;
@@ -596,17 +602,17 @@ __global__ __launch_bounds__(256) void init_adjoint_final_high_kernel(const Tube
 
 template <typename Real, int QPT, int NVT>
 hipError_t adjoint_stage_t(int nx, int Q, const AdjArgs<Real>& a, hipStream_t s) {
-  const int nred = (nx + kRedCells - 1) / kRedCells, nfx = (nx + 1 + 255) / 256;
+  const int nred = (nx + red_cells<Real>() - 1) / red_cells<Real>(), nfx = (nx + 1 + 255) / 256;
   hipLaunchKernelGGL((adj_reduce_faces_kernel<Real, QPT, NVT>), dim3(nred + nfx * Q), dim3(256), 0, s, a, nred, nfx);
   hipLaunchKernelGGL(adj_combine_kernel<Real>, dim3((nx + 255) / 256, Q), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-// The high-order form: its reduction in a launch of its own (64 KB of LDS
-// for the weights of a node), then the face blocks alone and the combine.
+// The high-order form: its reduction in a launch of its own (up to 64 KB of
+// LDS for the weights of a node), then the face blocks alone and the combine.
 template <typename Real>
 hipError_t adjoint_stage_high(int nx, int Q, const AdjArgs<Real>& a, hipStream_t s) {
-  const int nred = (nx + kRedCells - 1) / kRedCells, nfx = (nx + 1 + 255) / 256;
+  const int nred = (nx + red_cells<Real>() - 1) / red_cells<Real>(), nfx = (nx + 1 + 255) / 256;
   hipLaunchKernelGGL(adj_reduce_high_kernel<Real>, dim3(nred), dim3(256), 0, s, a);
   hipLaunchKernelGGL((adj_reduce_faces_kernel<Real, 3, 5>), dim3(nfx * Q), dim3(256), 0, s, a, 0, nfx);
   hipLaunchKernelGGL(adj_combine_kernel<Real>, dim3((nx + 255) / 256, Q), dim3(256), 0, s, a);
