@@ -27,9 +27,13 @@
 // b = 4s + l / 16, which is the B-operand layout of the MFMA (B[k][n] in lane
 // 16k + n); the A operands Ze, Zo (A[m][k] in lane 16k + m) are staged in LDS
 // once per tile; result register r of lane l is row 4r + l / 16, column
-// l % 16.  Each K-step's E_b, O_b (two reciprocals, two Horner chains over
+// l % 16.  Each K-step's E_b, O_b (one reciprocal, two Horner chains over
 // the node's Laguerre values, held in scalar registers for a compile-time
-// N_p) are formed just before the four products that consume them: FP64
+// N_p) are formed just before the four products that consume them.  The two
+// denominators share the reciprocal: (gamma - x u)(gamma + x u) =
+// 1 + u^2 (1 - x^2) (as gamma^2 = 1 + u^2), which is at least 1, so
+// 1/(gamma -+ x u) = (gamma +- x u) / (1 + u^2 (1 - x^2)); the factor pref / 2
+// is applied to the results instead of to every E_b, O_b.  FP64
 // vector instructions do not issue while the FP64 matrix pipe is busy, so a
 // step costs its products plus that vector work, and the register budget is
 // capped at 128 so that four waves per SIMD keep the matrix pipe fed.
@@ -134,7 +138,7 @@ void feq_kernel(FeqArgs<Real> a) {
         u = st[2];
         gam = sqrt(1.0 + u * u);
       }
-      const double r = T / T0, pref = n / (4.0 * T * T0 * T0);
+      const double r = T / T0, hpref = 0.5 * (n / (4.0 * T * T0 * T0)), u2 = u * u;
       for (int node = blockIdx.y; node < qp; node += gridDim.y) {
         const cptr<double> Lrow = itab + int64_t(irow + node) * kIStride + 4;  // L_l(p_node)
         // RT row tiles of Ze / Zo at most: 2 RT accumulators
@@ -158,7 +162,8 @@ void feq_kernel(FeqArgs<Real> a) {
             if (s < ns) {
               // B operands of this K-step: E_b, O_b of pair b = 4s + quarter
               const double xb = xs[4 * s + quarter];
-              const double yp = recip(gam - xb * u), ym = recip(gam + xb * u);
+              const double rd = recip(fma(u2, fma(-xb, xb, 1.0), 1.0));
+              const double yp = fma(xb, u, gam) * rd, ym = fma(-xb, u, gam) * rd;
               const double qpl = 1.0 - r * yp, qmi = 1.0 - r * ym;
               double sp = Lv[NP], sm = Lv[NP];
 #pragma unroll
@@ -167,7 +172,7 @@ void feq_kernel(FeqArgs<Real> a) {
                 sm = sm * qmi + Lv[k];
               }
               const double gp = yp * yp * sp, gm = ym * ym * sm;
-              const double E = pref * (gp + gm), O = pref * (gp - gm);
+              const double E = gp + gm, O = gp - gm;
               ce[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ae[4 * s], E, ce[0], 0, 0, 0);
               co[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(ao[4 * s], O, co[0], 0, 0, 0);
 #pragma unroll
@@ -198,8 +203,8 @@ void feq_kernel(FeqArgs<Real> a) {
               const int j = (jt0 + jt) * 16 + 4 * rr + quarter;
               if (j < half) {
                 const int jm = qx - 1 - j;
-                orow[int64_t(j) * ldx] = Real(0.5 * (ce[rr] + co[rr]));
-                if (jm != j) orow[int64_t(jm) * ldx] = Real(0.5 * (ce[rr] - co[rr]));
+                orow[int64_t(j) * ldx] = Real(hpref * (ce[rr] + co[rr]));
+                if (jm != j) orow[int64_t(jm) * ldx] = Real(hpref * (ce[rr] - co[rr]));
               }
             }
           };

@@ -217,6 +217,13 @@ void stage_kernel(StageArgs<Real> a) {
   // (written for this stage's input by the equilibrium pre-pass) instead of
   // being evaluated from projection coefficients
   constexpr bool kHigh = NVT < 0;
+  // In the pipelined FP32 stages of a high-order group the pre-pass of the
+  // next piece runs beside this kernel on another stream and its matrix-core
+  // waves share the SIMDs with these: a higher issue priority for the stage's
+  // waves keeps its (memory-bound) loads going out while the pre-pass takes
+  // the remaining issue slots.  Every wave of a launch gets the same priority,
+  // so a launch that runs alone is unaffected.
+  if constexpr (kHigh) __builtin_amdgcn_s_setprio(1);
   constexpr int ND = kHigh ? 1 : NVT + 1;
   using Vec = typename LdsVec<Real>::type;
   __shared__ __attribute__((aligned(16))) Real tile[NH][TILE + 6][V];
