@@ -25,7 +25,7 @@
  * - Work is queued asynchronously on the HIP stream given to rlb_bind (NULL
  *   means the legacy default stream).  Calls documented as "synchronizes" wait
  *   for that stream.  A lattice must not be used from two threads at once.
- *   An FP32 lattice with a high-order tube (n_v > 7) also owns one side stream
+ *   A lattice with a high-order tube (n_v > 7) also owns one side stream
  *   (default priority, created by its first rlb_bind on the device current
  *   then) on which the equilibrium pre-pass of a stage runs piece by piece,
  *   ordered with events against the stage kernels on the lattice's stream; a

@@ -323,11 +323,11 @@ void make_side(rlb_lattice* L) {
   L->side_device = dev;
 }
 
-// Pieces of a high-order stage (1: no pipelining): FP32 only, with the side
-// stream on the current device, one workgroup per tile and at least two tiles
-// per CU in every piece.
+// Pieces of a high-order stage (1: no pipelining): with the side stream on the
+// current device, one workgroup per tile and at least two tiles per CU in
+// every piece.
 int pipe_pieces(const rlb_lattice* L, const LaunchShape& ls, int nitems) {
-  if (L->prec != RLB_FP32 || !L->side || ls.nodes > 1) return 1;
+  if (!L->side || ls.nodes > 1) return 1;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev != L->side_device) return 1;
   return std::max(1, std::min(kPipePieces, nitems / (2 * std::max(1, L->cu_count))));

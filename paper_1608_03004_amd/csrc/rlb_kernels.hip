@@ -217,9 +217,9 @@ void stage_kernel(StageArgs<Real> a) {
   // (written for this stage's input by the equilibrium pre-pass) instead of
   // being evaluated from projection coefficients
   constexpr bool kHigh = NVT < 0;
-  // In the pipelined FP32 stages of a high-order group the pre-pass of the
-  // next piece runs beside this kernel on another stream and its matrix-core
-  // waves share the SIMDs with these: a higher issue priority for the stage's
+  // In the pipelined stages of a high-order group the pre-pass of the next
+  // piece runs beside this kernel on another stream and its matrix-core waves
+  // share the SIMDs with these: a higher issue priority for the stage's
   // waves keeps its (memory-bound) loads going out while the pre-pass takes
   // the remaining issue slots.  Every wave of a launch gets the same priority,
   // so a launch that runs alone is unaffected.

@@ -463,12 +463,11 @@ def test_full_size_high_order_window(torch_cuda, precision, tol):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_pipelined_high_order_stages_match_the_single_launch_bitwise(torch_cuda, precision):
-    # 2^18 cells, N_v = 63: in FP32 the default schedule pipelines the
-    # equilibrium pre-pass over two pieces of the work list, 64-cell tiles
-    # over eight, and graph replay captures the side stream's fork and the
-    # per-piece joins; a node-split launch (split_below above the tile count)
-    # runs the pre-pass unpipelined on the lattice's stream, as the FP64 form
-    # always does.  All four give the same bits.
+    # 2^18 cells, N_v = 63: the default schedule pipelines the equilibrium
+    # pre-pass over two pieces of the work list, 64-cell tiles over eight, and
+    # graph replay captures the side stream's fork and the per-piece joins; a
+    # node-split launch (split_below above the tile count) runs the pre-pass
+    # unpipelined on the lattice's stream.  All four give the same bits.
     params = [dict(nx=1 << 18, q_xi=64, q_p=4, n_v=63, tau=1e-2)]
     runs = []
     for sched in (dict(tile=256), dict(tile=256, split_below=1 << 30), dict(tile=64), dict(tile=256, graph_steps=2)):
