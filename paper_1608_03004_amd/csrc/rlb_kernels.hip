@@ -193,10 +193,13 @@ struct Moments3 {
 };
 
 // Waves per SIMD the register allocation must allow.  The first stage of a
-// step (no f^n stream) of the Q_p <= 4 groups runs at 4 waves with every value
-// in registers (5 waves with a few spilled registers measured 2 % slower in
-// FP32); stages 2 and 3 of those groups are bandwidth-bound and keep every
-// value in registers at the compiler's choice (4 waves in FP32).  The FP32
+// step (no f^n stream) of the Q_p <= 4 groups runs at 4 waves: in FP32 with
+// every value in registers (5 waves with a few spilled registers measured 2 %
+// slower), in FP64 with 148 bytes per lane spilled, which still beats 3 waves
+// without spills (3.65 against 3.70 ms per FP64 step of a 2^20-cell tube with
+// Q = 64 x 4); stages 2 and 3 of those groups are bandwidth-bound and keep
+// every value in registers at the compiler's choice (4 waves in FP32, 3 in
+// FP64, where 4 waves spill and measured 3.74 ms).  The FP32
 // Q_p <= 8 group runs at 4 waves instead of the compiler's 3 (a 2^19-cell tube
 // with Q = 64 x 5: 1.35 against 1.41 ms per step); its FP64 form keeps all
 // its coefficients in registers (3 waves measured 18 % slower).  The
