@@ -337,9 +337,11 @@ int pipe_pieces(const rlb_lattice* L, const LaunchShape& ls, int nitems) {
 // records are `rec`, or with rec == nullptr of the masked tubes' initial side
 // states, into `out`.  Large groups take one workgroup per tile for all radial
 // nodes (the tables are staged once per tile); small ones spread the nodes
-// over a second grid dimension.
+// over a second grid dimension.  max_grid > 0 caps the workgroups (each then
+// loops over several tiles).
 template <typename Real>
-hipError_t equilibrium_pass(rlb_lattice* L, const Group& g, const double* rec, void* out, hipStream_t s) {
+hipError_t equilibrium_pass(rlb_lattice* L, const Group& g, const double* rec, void* out, hipStream_t s,
+                            int max_grid = 0) {
   FeqArgs<Real> f;
   f.tubes = L->dev<TubeDev>(L->off_tubes);
   f.items = L->dev<WorkItem>(L->off_items) + g.item_begin;
@@ -354,7 +356,7 @@ hipError_t equilibrium_pass(rlb_lattice* L, const Group& g, const double* rec, v
   f.row_tiles = (g.zj_max + 15) / 16;
   LaunchShape ls;
   ls.tile = L->sched.tile;
-  ls.grid = f.nitems;
+  ls.grid = max_grid > 0 ? std::min(f.nitems, max_grid) : f.nitems;
   ls.nodes = f.nitems < 2 * std::max(1, L->cu_count) ? g.qp_max : 1;
   return launch_feq(sizeof(Real) == 4, ls, &f, s);
 }
@@ -394,6 +396,11 @@ hipError_t stage_group(rlb_lattice* L, const Group& g, int stage, const void* fi
       // previous stage's kernel of the same piece (or, first in a call, for
       // everything before on s); the stage kernel of a piece waits for its
       // piece's pre-pass, and the stage kernels keep their order on s (halos).
+      // In FP64 the stage kernel is the slower of the two: a piece's pre-pass
+      // then takes one workgroup per CU, looping over its tiles, which leaves
+      // registers for more waves of the memory-bound stage kernel beside it
+      // (in FP32 the pre-pass is the slower one and takes a workgroup per tile).
+      const int pre_grid = sizeof(Real) == 8 ? std::max(1, L->cu_count) : 0;
       if (!L->pipe_forked) {
         if ((e = hipEventRecord(L->ev_fork, s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(L->side, L->ev_fork, 0)) != hipSuccess) return e;
@@ -404,7 +411,7 @@ hipError_t stage_group(rlb_lattice* L, const Group& g, int stage, const void* fi
         gp.item_begin = g.item_begin + b;
         gp.item_end = g.item_begin + en;
         if (L->pipe_forked && (e = hipStreamWaitEvent(L->side, L->ev_stage[p], 0)) != hipSuccess) return e;
-        if ((e = equilibrium_pass<Real>(L, gp, rec_in, L->ws + L->off_feq, L->side)) != hipSuccess) return e;
+        if ((e = equilibrium_pass<Real>(L, gp, rec_in, L->ws + L->off_feq, L->side, pre_grid)) != hipSuccess) return e;
         if ((e = hipEventRecord(L->ev_pre[p], L->side)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(s, L->ev_pre[p], 0)) != hipSuccess) return e;
         StageArgs<Real> ap = a;
