@@ -286,13 +286,13 @@ def _whole_tube_checks(lat, params, nsteps, tot0, tol, tot_tol):
     assert drift.max() < tot_tol
 
 
-def _window_check(params, precision, nsteps, half=256, tol=1e-12, outer_tol=None, tot_tol=None):
+def _window_check(params, precision, nsteps, half=256, tol=1e-12, outer_tol=None, tot_tol=None, schedule=None):
     """Full-size run on the GPU; the oracle follows a window around z = 0, and
     every cell outside the disturbed region is checked against its side's
     initial state."""
     from oracle import oracle as O
     nx = params["nx"]
-    lat = _lattice([params], precision=precision)
+    lat = _lattice([params], precision=precision, schedule=schedule)
     dt = lat.info(0)["dt"]
     lat.set_initial_state(SOD_L, SOD_R)
     tot0 = lat.totals(0)
@@ -319,12 +319,16 @@ def _window_check(params, precision, nsteps, half=256, tol=1e-12, outer_tol=None
 
 
 def test_full_size_sod_large_fp64_window(torch_cuda):
-    # N_x = 2^20, Q = 64 x 4 (the large Sod configuration), FP64
-    _window_check(dict(nx=1 << 20, q_xi=64, q_p=4, tau=1e-2), "fp64", 4)
+    # N_x = 2^20, Q = 64 x 4 (the large Sod configuration), FP64, in the
+    # schedule the benchmark times (64-cell tiles)
+    import bench
+    _window_check(dict(nx=1 << 20, q_xi=64, q_p=4, tau=1e-2), "fp64", 4, schedule=bench.head_schedule("fp64"))
 
 
 def test_full_size_sod_large_fp32_window(torch_cuda):
-    _window_check(dict(nx=1 << 20, q_xi=64, q_p=4, tau=1e-4), "fp32", 4, tol=1e-5)
+    import bench
+    _window_check(dict(nx=1 << 20, q_xi=64, q_p=4, tau=1e-4), "fp32", 4, tol=1e-5,
+                  schedule=bench.head_schedule("fp32"))
 
 
 def test_full_size_ballistic_fp32_window(torch_cuda):
